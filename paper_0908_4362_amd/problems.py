@@ -1,0 +1,262 @@
+"""Seeded synthetic initial states for the MHD step (numpy only).
+
+These generators build the test problems of Wong et al. (Sec. 5: Brio-Wu shock
+tube, Orszag-Tang vortex, blast waves) and smooth states for checking the
+solver (linear MHD waves with closed-form solutions, random smooth states).
+They only sample initial conditions; none of the solver's arithmetic lives
+here. Both the oracle and the GPU library consume these states.
+
+Conventions: cells are cubes of width h = 1 / max(nx, ny, nz) (the solver
+works in unit cells), so the box is [0, nx h) x [0, ny h) x [0, nz h); periodic
+patterns use whole periods of each box side. A state is a float64 array of shape (8, nz, ny, nx) holding
+rho, m_x, m_y, m_z, E, B_x, B_y, B_z with x fastest. B_d is sampled on the
+lower d-face of each cell (Sec. 3, eq. equat_b). Where the field is not
+constant along its own axis it is built as the discrete curl of an edge vector
+potential, so its discrete divergence vanishes to round-off. The total energy
+uses the analytic field at the cell centre. In code units (unit cells) a
+physical time t is t / h.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+MASTER_SEED = 9084362
+
+
+def cell_width(nx, ny, nz):
+    return 1.0 / max(nx, ny, nz)
+
+
+def _centres(n, h):
+    return (np.arange(n) + 0.5) * h
+
+
+def _faces(n, h):
+    return np.arange(n) * h
+
+
+def _grid(nx, ny, nz, kind):
+    """Coordinates (x, y, z) broadcastable to (nz, ny, nx); kind gives, per axis,
+    'c' for cell centres or 'f' for lower faces."""
+    h = cell_width(nx, ny, nz)
+    ax = []
+    for n, k in zip((nx, ny, nz), kind):
+        ax.append(_centres(n, h) if k == "c" else _faces(n, h))
+    x = ax[0][None, None, :]
+    y = ax[1][None, :, None]
+    z = ax[2][:, None, None]
+    return x, y, z
+
+
+def assemble(rho, vel, p, bface, bcentre, gamma, shape):
+    """State array from primitive cell values, face fields and centred field.
+
+    rho, p: cell values; vel, bcentre: 3-tuples of cell values; bface: 3-tuple
+    of face values (each broadcastable to shape = (nz, ny, nx)).
+    """
+    nz, ny, nx = shape
+    s = np.zeros((8, nz, ny, nx), dtype=np.float64)
+    rho = np.broadcast_to(np.asarray(rho, dtype=np.float64), shape)
+    p = np.broadcast_to(np.asarray(p, dtype=np.float64), shape)
+    v = [np.broadcast_to(np.asarray(c, dtype=np.float64), shape) for c in vel]
+    bc = [np.broadcast_to(np.asarray(c, dtype=np.float64), shape) for c in bcentre]
+    s[0] = rho
+    for a in range(3):
+        s[1 + a] = rho * v[a]
+        s[5 + a] = np.broadcast_to(np.asarray(bface[a], dtype=np.float64), shape)
+    kin = 0.5 * rho * (v[0] ** 2 + v[1] ** 2 + v[2] ** 2)
+    mag = 0.5 * (bc[0] ** 2 + bc[1] ** 2 + bc[2] ** 2)
+    s[4] = p / (gamma - 1.0) + kin + mag
+    return s
+
+
+def curl_faces(ax_fn, ay_fn, az_fn, nx, ny, nz):
+    """Face fields of the discrete curl of an edge vector potential.
+
+    a_x lives on x-edges (cell-centre x, face y, face z), a_y on y-edges and a_z
+    on z-edges. Each *_fn(x, y, z) is evaluated on the needed edge points
+    (periodic potentials). Differences are taken over one cell (width h)."""
+    h = cell_width(nx, ny, nz)
+
+    def ev(fn, x, y, z):
+        return np.broadcast_to(fn(x, y, z), (nz, ny, nx)).astype(np.float64)
+
+    xc, yc, zc = _grid(nx, ny, nz, "ccc")
+    xf, yf, zf = _grid(nx, ny, nz, "fff")
+    bx = (ev(az_fn, xf, yf + h, zc) - ev(az_fn, xf, yf, zc)) / h - (
+        ev(ay_fn, xf, yc, zf + h) - ev(ay_fn, xf, yc, zf)) / h
+    by = (ev(ax_fn, xc, yf, zf + h) - ev(ax_fn, xc, yf, zf)) / h - (
+        ev(az_fn, xf + h, yf, zc) - ev(az_fn, xf, yf, zc)) / h
+    bz = (ev(ay_fn, xf + h, yc, zf) - ev(ay_fn, xf, yc, zf)) / h - (
+        ev(ax_fn, xc, yf + h, zf) - ev(ax_fn, xc, yf, zf)) / h
+    return bx, by, bz
+
+
+# --------------------------------------------------------------------------
+# Problems of the paper (Sec. 5)
+# --------------------------------------------------------------------------
+
+def brio_wu(n: int, gamma: float = 2.0, axis: int = 0, ntrans: int = 1):
+    """Brio-Wu shock tube (Sec. 5.1.1) laid along `axis` (n cells), interface at
+    0.5 (cell centres below 0.5 take the left state); the normal field is 0.75
+    and the first transverse field +1 / -1. Transverse axes have ntrans cells."""
+    shape_xyz = [ntrans, ntrans, ntrans]
+    shape_xyz[axis] = n
+    nx, ny, nz = shape_xyz
+    shape = (nz, ny, nx)
+    pos = (np.arange(n) + 0.5) / n
+    left = pos < 0.5
+    sel = [None, None, None]
+    sel[2 - axis] = slice(None)
+    L = left[tuple(sel)]
+    rho = np.where(L, 1.0, 0.125)
+    p = np.where(L, 1.0, 0.1)
+    t1 = (axis + 1) % 3
+    bvals = [0.0, 0.0, 0.0]
+    bvals[axis] = 0.75
+    bt = np.where(L, 1.0, -1.0)
+    bcomp = [np.zeros(shape) + bvals[a] for a in range(3)]
+    bcomp[t1] = np.broadcast_to(bt, shape).astype(np.float64)
+    return assemble(rho, (0.0, 0.0, 0.0), p, bcomp, bcomp, gamma, shape)
+
+
+def orszag_tang(n: int, nz: int = 1, gamma: float = 5.0 / 3.0):
+    """Orszag-Tang vortex (Sec. 5.2.1) on n x n (x nz, extruded along z)."""
+    b0 = 1.0 / math.sqrt(4.0 * math.pi)
+    shape = (nz, n, n)
+    xc, yc, _ = _grid(n, n, nz, "ccc")
+    rho = 25.0 / (36.0 * math.pi)
+    p = 5.0 / (12.0 * math.pi)
+    vx = -np.sin(2 * math.pi * yc)
+    vy = np.sin(2 * math.pi * xc)
+    # B_x on x-faces depends on y only, B_y on y-faces on x only: the face values
+    # equal the centre values and the field is exactly divergence free.
+    bx = -b0 * np.sin(2 * math.pi * yc) + 0.0 * xc
+    by = b0 * np.sin(4 * math.pi * xc) + 0.0 * yc
+    bz = np.zeros(shape)
+    return assemble(rho, (vx, vy, 0.0), p, (bx, by, bz), (bx, by, bz), gamma, shape)
+
+
+def blast(n: int, p_in: float = 10.0, p_out: float = 0.1, radius: float = 0.1,
+          bvec=(1.0 / math.sqrt(2.0), 1.0 / math.sqrt(2.0), 0.0), gamma: float = 5.0 / 3.0,
+          ny: int | None = None, nz: int | None = None, centre=(0.5, 0.5, 0.5)):
+    """Blast wave (Sec. 5.2.2, 5.3): rho = 1, v = 0, uniform B, p = p_in for cell
+    centres strictly inside the sphere, p_out elsewhere."""
+    ny = n if ny is None else ny
+    nz = n if nz is None else nz
+    shape = (nz, ny, n)
+    x, y, z = _grid(n, ny, nz, "ccc")
+    r2 = (x - centre[0]) ** 2 + (y - centre[1]) ** 2
+    if nz > 1:
+        r2 = r2 + (z - centre[2]) ** 2
+    p = np.where(r2 < radius * radius, p_in, p_out)
+    b = tuple(np.full(shape, float(c)) for c in bvec)
+    return assemble(1.0, (0.0, 0.0, 0.0), p, b, b, gamma, shape)
+
+
+# --------------------------------------------------------------------------
+# Smooth states with known behaviour
+# --------------------------------------------------------------------------
+
+def uniform(nx, ny, nz, rho=1.0, vel=(0.0, 0.0, 0.0), p=1.0, bvec=(0.0, 0.0, 0.0), gamma=5.0 / 3.0):
+    shape = (nz, ny, nx)
+    b = tuple(np.full(shape, float(c)) for c in bvec)
+    return assemble(rho, vel, p, b, b, gamma, shape)
+
+
+def wavevector(nx, ny, nz, kvec):
+    """Physical wave vector of integer mode numbers kvec on the box."""
+    h = cell_width(nx, ny, nz)
+    side = np.array([nx * h, ny * h, nz * h])
+    return 2.0 * math.pi * np.asarray(kvec, dtype=np.float64) / side
+
+
+def linear_wave(nx, ny, nz, kvec, rho0, p0, vel0, bvec0, gamma, drho=0.0, dv=(0.0, 0.0, 0.0), dp=0.0,
+                db=0.0, db_dir=(0.0, 0.0, 0.0), phase=0.0):
+    """Plane wave on a uniform background: every perturbation varies as
+    sin(theta), theta = k . x - phase with k_a = 2 pi kvec_a / L_a (kvec
+    integer per axis, L_a the box side) so the pattern is periodic.
+
+    The field perturbation db * db_dir (db_dir a unit vector orthogonal to kvec)
+    is the discrete curl of a = db/|k| (k_hat x db_dir) cos(theta) on the edges,
+    so it is divergence free to round-off."""
+    shape = (nz, ny, nx)
+    k = wavevector(nx, ny, nz, kvec)
+    kn = float(np.linalg.norm(k))
+    ndir = np.asarray(db_dir, dtype=np.float64)
+
+    def theta(x, y, z):
+        return k[0] * x + k[1] * y + k[2] * z - phase
+
+    xc, yc, zc = _grid(nx, ny, nz, "ccc")
+    th = theta(xc, yc, zc)
+    sn = np.sin(th)
+    rho = rho0 + drho * sn
+    vel = tuple(vel0[a] + dv[a] * sn for a in range(3))
+    p = p0 + dp * sn
+    if db != 0.0:
+        w = np.cross(k / kn, ndir) * (db / kn)
+
+        def comp(a):
+            return lambda x, y, z: w[a] * np.cos(theta(x, y, z))
+
+        bx, by, bz = curl_faces(comp(0), comp(1), comp(2), nx, ny, nz)
+        bface = (bx + bvec0[0], by + bvec0[1], bz + bvec0[2])
+    else:
+        bface = tuple(np.full(shape, float(bvec0[a])) for a in range(3))
+    bcen = tuple(bvec0[a] + db * ndir[a] * sn for a in range(3))
+    return assemble(rho, vel, p, bface, bcen, gamma, shape)
+
+
+def random_smooth(nx, ny, nz, seed, gamma=5.0 / 3.0, amp=0.2, modes=3, bmean=(0.6, -0.3, 0.4), vmean=(0.1, -0.2, 0.15)):
+    """Smooth periodic state with random low Fourier modes (seeded, NumPy PCG64):
+    positive density and pressure, non-zero velocity, and a field made of a
+    uniform part plus the discrete curl of a random periodic potential."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = (nz, ny, nx)
+    xc, yc, zc = _grid(nx, ny, nz, "ccc")
+    h = cell_width(nx, ny, nz)
+    side = (nx * h, ny * h, nz * h)
+
+    def kphys(kx, ky, kz):
+        return (2 * math.pi * kx / side[0], 2 * math.pi * ky / side[1], 2 * math.pi * kz / side[2])
+
+    def field(x, y, z, coef):
+        out = 0.0
+        for (kx, ky, kz, a, ph) in coef:
+            k = kphys(kx, ky, kz)
+            out = out + a * np.sin(k[0] * x + k[1] * y + k[2] * z + ph)
+        return out
+
+    def draw():
+        return [(int(rng.integers(0, modes + 1)) if nx > 1 else 0,
+                 int(rng.integers(0, modes + 1)) if ny > 1 else 0,
+                 int(rng.integers(0, modes + 1)) if nz > 1 else 0,
+                 float(rng.uniform(-1, 1)), float(rng.uniform(0, 2 * math.pi))) for _ in range(4)]
+
+    rho = 1.0 + amp * field(xc, yc, zc, draw())
+    p = 1.0 + amp * field(xc, yc, zc, draw())
+    vel = tuple(vmean[a] + amp * field(xc, yc, zc, draw()) for a in range(3))
+    acoef = [draw() for _ in range(3)]
+    scale = amp / (2 * math.pi * max(modes, 1))
+    pot = [lambda x, y, z, c=acoef[a]: scale * field(x, y, z, c) for a in range(3)]
+    bx, by, bz = curl_faces(pot[0], pot[1], pot[2], nx, ny, nz)
+    bface = (bx + bmean[0], by + bmean[1], bz + bmean[2])
+
+    # analytic centred field: curl of the continuous potential at cell centres
+    def dfield(x, y, z, coef, axis):
+        out = 0.0
+        for (kx, ky, kz, a, ph) in coef:
+            k = kphys(kx, ky, kz)
+            out = out + a * k[axis] * np.cos(k[0] * x + k[1] * y + k[2] * z + ph)
+        return out
+
+    def d(a, axis):
+        return scale * dfield(xc, yc, zc, acoef[a], axis)
+
+    bcx = bmean[0] + d(2, 1) - d(1, 2)
+    bcy = bmean[1] + d(0, 2) - d(2, 0)
+    bcz = bmean[2] + d(1, 0) - d(0, 1)
+    return assemble(rho, vel, p, bface, (bcx, bcy, bcz), gamma, shape)
