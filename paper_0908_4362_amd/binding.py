@@ -1,0 +1,237 @@
+"""Thin ctypes binding of the C ABI in include/mhd.h (same names).
+
+Only argument marshalling lives here: every step of the computation runs in
+the HIP library. Host states are numpy arrays of shape (8, nz, ny, nx) (or any
+contiguous buffer of 8*nx*ny*nz elements of the handle's dtype); device
+states are torch tensors on the GPU (or raw device addresses).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmhd.so")
+
+MHD_OK, MHD_ERR_ARG, MHD_ERR_OOM, MHD_ERR_DEVICE, MHD_ERR_NONFINITE = 0, -1, -2, -3, -4
+MHD_BC_PERIODIC, MHD_BC_OUTFLOW = 0, 1
+MHD_F32, MHD_F64 = 0, 1
+MHD_K_CFL, MHD_K_FLUID_X, MHD_K_FLUID_Y, MHD_K_FLUID_Z, MHD_K_CT_X, MHD_K_CT_Y, MHD_K_CT_Z, MHD_K_COUNT = range(8)
+KERNEL_KINDS = ("cfl", "fluid_x", "fluid_y", "fluid_z", "ct_x", "ct_y", "ct_z")
+
+_lib = None
+
+
+class MHDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("mhd error %d: %s" % (code, msg))
+        self.code = code
+
+
+def lib():
+    """Load libmhd.so; fail loudly if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmhd.so is not built; run `python -m paper_0908_4362_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        sig = {
+            "mhd_create": ([i, i, i, d, i, i, ctypes.POINTER(vp)], i),
+            "mhd_destroy": ([vp], i),
+            "mhd_set_stream": ([vp, vp], i),
+            "mhd_set_state": ([vp, vp], i),
+            "mhd_set_state_device": ([vp, vp], i),
+            "mhd_get_state": ([vp, vp], i),
+            "mhd_get_state_device": ([vp, vp], i),
+            "mhd_step": ([vp, i, d], i),
+            "mhd_divb_max": ([vp, ctypes.POINTER(d)], i),
+            "mhd_get_time": ([vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64)], i),
+            "mhd_set_time": ([vp, d, ctypes.c_int64], i),
+            "mhd_set_stop_time": ([vp, d], i),
+            "mhd_last_error": ([], ctypes.c_char_p),
+            "mhd_fluid_sweep": ([vp, i, d], i),
+            "mhd_ct_sweep": ([vp, i, d], i),
+            "mhd_cmax": ([vp, ctypes.POINTER(d)], i),
+            "mhd_step_dt": ([vp, d, ctypes.c_int64], i),
+            "mhd_state_bytes": ([i, i, i, i], ctypes.c_size_t),
+            "mhd_timing": ([vp, i], i),
+            "mhd_timing_read": ([vp, i, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64)], i),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def mhd_last_error() -> str:
+    return lib().mhd_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != MHD_OK:
+        raise MHDError(rc, mhd_last_error())
+
+
+def _np_dtype(dtype: int):
+    return np.float64 if dtype == MHD_F64 else np.float32
+
+
+def _dev_ptr(x) -> int:
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def mhd_create(nx: int, ny: int, nz: int, gamma: float, bc: int, dtype: int):
+    h = ctypes.c_void_p()
+    _check(lib().mhd_create(nx, ny, nz, gamma, bc, dtype, ctypes.byref(h)))
+    return h
+
+
+def mhd_destroy(h):
+    _check(lib().mhd_destroy(h))
+
+
+def mhd_set_stream(h, stream):
+    """stream: a torch.cuda.Stream, a raw hipStream_t address, or None."""
+    ptr = None if stream is None else (stream if isinstance(stream, int) else int(stream.cuda_stream))
+    _check(lib().mhd_set_stream(h, ptr))
+
+
+def mhd_set_state(h, host_state: np.ndarray):
+    a = np.ascontiguousarray(host_state)
+    _check(lib().mhd_set_state(h, a.ctypes.data_as(ctypes.c_void_p)))
+
+
+def mhd_set_state_device(h, dev_state):
+    _check(lib().mhd_set_state_device(h, ctypes.c_void_p(_dev_ptr(dev_state))))
+
+
+def mhd_get_state(h, out: np.ndarray):
+    if not out.flags["C_CONTIGUOUS"]:
+        raise ValueError("output array must be C-contiguous")
+    _check(lib().mhd_get_state(h, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def mhd_get_state_device(h, dev_state):
+    _check(lib().mhd_get_state_device(h, ctypes.c_void_p(_dev_ptr(dev_state))))
+
+
+def mhd_step(h, n: int, cfl: float):
+    _check(lib().mhd_step(h, n, cfl))
+
+
+def mhd_divb_max(h) -> float:
+    v = ctypes.c_double()
+    _check(lib().mhd_divb_max(h, ctypes.byref(v)))
+    return v.value
+
+
+def mhd_get_time(h):
+    t = ctypes.c_double()
+    s = ctypes.c_int64()
+    _check(lib().mhd_get_time(h, ctypes.byref(t), ctypes.byref(s)))
+    return t.value, s.value
+
+
+def mhd_set_time(h, t: float, s: int):
+    _check(lib().mhd_set_time(h, t, s))
+
+
+def mhd_set_stop_time(h, t_stop):
+    _check(lib().mhd_set_stop_time(h, -1.0 if t_stop is None else float(t_stop)))
+
+
+def mhd_fluid_sweep(h, axis: int, dt: float):
+    _check(lib().mhd_fluid_sweep(h, axis, dt))
+
+
+def mhd_ct_sweep(h, axis: int, dt: float):
+    _check(lib().mhd_ct_sweep(h, axis, dt))
+
+
+def mhd_cmax(h) -> float:
+    v = ctypes.c_double()
+    _check(lib().mhd_cmax(h, ctypes.byref(v)))
+    return v.value
+
+
+def mhd_step_dt(h, dt: float, s_order: int):
+    _check(lib().mhd_step_dt(h, dt, s_order))
+
+
+def mhd_state_bytes(nx: int, ny: int, nz: int, dtype: int) -> int:
+    return int(lib().mhd_state_bytes(nx, ny, nz, dtype))
+
+
+def mhd_timing(h, enable: bool):
+    _check(lib().mhd_timing(h, 1 if enable else 0))
+
+
+def mhd_timing_read(h, kind: int):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().mhd_timing_read(h, kind, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+class Solver:
+    """Owning wrapper of one handle (host-side convenience; no computation)."""
+
+    def __init__(self, nx, ny, nz, gamma, bc=MHD_BC_PERIODIC, dtype=MHD_F64):
+        self.shape = (8, nz, ny, nx)
+        self.dtype = dtype
+        self.np_dtype = _np_dtype(dtype)
+        self.h = mhd_create(nx, ny, nz, gamma, bc, dtype)
+
+    def close(self):
+        if self.h is not None:
+            mhd_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, s: np.ndarray):
+        a = np.ascontiguousarray(s, dtype=self.np_dtype)
+        if a.size != int(np.prod(self.shape)):
+            raise ValueError("state has %d elements, expected %d" % (a.size, int(np.prod(self.shape))))
+        mhd_set_state(self.h, a)
+
+    def get_state(self) -> np.ndarray:
+        out = np.empty(self.shape, dtype=self.np_dtype)
+        return mhd_get_state(self.h, out)
+
+    def step(self, n: int, cfl: float = 0.7):
+        mhd_step(self.h, n, cfl)
+
+    def run_to(self, t_stop: float, cfl: float = 0.7, max_steps: int = 1000000, chunk: int = 64):
+        mhd_set_stop_time(self.h, t_stop)
+        steps = 0
+        while self.time()[0] < t_stop and steps < max_steps:
+            mhd_step(self.h, chunk, cfl)
+            steps += chunk
+
+    def time(self):
+        return mhd_get_time(self.h)
+
+    def divb_max(self) -> float:
+        return mhd_divb_max(self.h)
+
+    def cmax(self) -> float:
+        return mhd_cmax(self.h)

@@ -1,0 +1,511 @@
+// Host runtime and C ABI of the MHD step library (declared in include/mhd.h).
+//
+// A handle owns two ping-pong copies of the conserved fields (5 x N) and of
+// the face fields (3 x N) plus a device control block holding dt, t, the stop
+// time, the reduction scratch and a latched status word. Every sweep reads one
+// copy and writes the other, so a full step (6 fluid and 6 field sweeps)
+// returns both to the copy it started from.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/mhd.h"
+#include "mhd_internal.h"
+
+using mhd::Ctl;
+using mhd::Grid;
+
+struct mhd_solver {
+    Grid g;
+    double gamma;
+    int dtype;            // MHD_F32 / MHD_F64
+    size_t esize;         // bytes per element
+    void* u[2];           // conserved fields, ping-pong
+    void* b[2];           // face fields, ping-pong
+    int ucur, bcur;       // current copies
+    Ctl* ctl;             // device control block
+    hipStream_t stream;
+    long long s;          // step counter (host mirror; the sweep order needs it on the host)
+    int device;
+    // optional per-kernel timing with HIP events on the handle's stream
+    bool timing;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[MHD_K_COUNT];
+    std::vector<hipEvent_t> pool;
+    double total_ms[MHD_K_COUNT];
+    long long launches[MHD_K_COUNT];
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where)
+{
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return MHD_ERR_DEVICE;
+}
+
+#define HIPCHK(call, where)                            \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+hipEvent_t take_event(mhd_solver* h)
+{
+    if (!h->pool.empty()) {
+        hipEvent_t e = h->pool.back();
+        h->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch through f(), bracketed by events when timing is on.
+template <typename F>
+int timed(mhd_solver* h, int kind, F&& f, const char* where)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (h->timing) {
+        a = take_event(h);
+        b = take_event(h);
+        if (!a || !b) return fail(MHD_ERR_DEVICE, "hipEventCreate failed");
+        HIPCHK(hipEventRecord(a, h->stream), "hipEventRecord");
+    }
+    HIPCHK(f(), where);
+    if (h->timing) {
+        HIPCHK(hipEventRecord(b, h->stream), "hipEventRecord");
+        h->pending[kind].emplace_back(a, b);
+    }
+    return MHD_OK;
+}
+
+template <typename T>
+int fluid(mhd_solver* h, int axis, double dt)
+{
+    const T* uin = static_cast<const T*>(h->u[h->ucur]);
+    T* uout = static_cast<T*>(h->u[h->ucur ^ 1]);
+    const T* b = static_cast<const T*>(h->b[h->bcur]);
+    int rc = timed(h, MHD_K_FLUID_X + axis,
+                   [&] { return mhd::launch_fluid<T>(axis, uin, uout, b, h->g, h->gamma, h->ctl, dt, h->stream); },
+                   "fluid sweep launch");
+    if (rc) return rc;
+    h->ucur ^= 1;
+    return MHD_OK;
+}
+
+template <typename T>
+int ct(mhd_solver* h, int axis, double dt)
+{
+    const T* u = static_cast<const T*>(h->u[h->ucur]);
+    const T* bin = static_cast<const T*>(h->b[h->bcur]);
+    T* bout = static_cast<T*>(h->b[h->bcur ^ 1]);
+    int rc = timed(h, MHD_K_CT_X + axis,
+                   [&] { return mhd::launch_ct<T>(axis, u, bin, bout, h->g, h->ctl, dt, h->stream); },
+                   "field sweep launch");
+    if (rc) return rc;
+    h->bcur ^= 1;
+    return MHD_OK;
+}
+
+// The 12 sweeps of one full step with sweep-order index s (eq. L_sequence):
+// forward L_d = fluid_d then the field update along d; reverse L_d with the
+// field update first; axis order (x,y,z), (z,x,y), (y,z,x) by s mod 3.
+template <typename T>
+int sweeps(mhd_solver* h, long long s, double dt)
+{
+    static const int perm[3][3] = {{0, 1, 2}, {2, 0, 1}, {1, 2, 0}};
+    const int* p = perm[((s % 3) + 3) % 3];
+    int rc;
+    for (int a = 0; a < 3; a++) {
+        if ((rc = fluid<T>(h, p[a], dt))) return rc;
+        if ((rc = ct<T>(h, p[a], dt))) return rc;
+    }
+    for (int a = 2; a >= 0; a--) {
+        if ((rc = ct<T>(h, p[a], dt))) return rc;
+        if ((rc = fluid<T>(h, p[a], dt))) return rc;
+    }
+    return MHD_OK;
+}
+
+template <typename T>
+int full_steps(mhd_solver* h, int n, double cfl)
+{
+    for (int k = 0; k < n; k++) {
+        const T* u = static_cast<const T*>(h->u[h->ucur]);
+        const T* b = static_cast<const T*>(h->b[h->bcur]);
+        int rc = timed(h, MHD_K_CFL, [&] { return mhd::launch_cfl<T>(u, b, h->g, h->gamma, cfl, h->ctl, h->stream); },
+                       "cfl launch");
+        if (rc) return rc;
+        rc = sweeps<T>(h, h->s, -1.0);
+        if (rc) return rc;
+        h->s += 1;
+    }
+    return MHD_OK;
+}
+
+int check(const mhd_solver* h)
+{
+    if (!h) return fail(MHD_ERR_ARG, "null handle");
+    return MHD_OK;
+}
+
+int set_current(const mhd_solver* h)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != h->device) HIPCHK(hipSetDevice(h->device), "hipSetDevice");
+    return MHD_OK;
+}
+
+int read_ctl(mhd_solver* h, Ctl* out)
+{
+    HIPCHK(hipMemcpyAsync(out, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream), "read control block");
+    HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
+    return MHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mhd_last_error(void) { return g_err.c_str(); }
+
+size_t mhd_state_bytes(int nx, int ny, int nz, int dtype)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || (dtype != MHD_F32 && dtype != MHD_F64)) return 0;
+    const size_t es = dtype == MHD_F64 ? 8 : 4;
+    return 2 * 8 * (size_t)nx * ny * nz * es + sizeof(Ctl);
+}
+
+int mhd_create(int nx, int ny, int nz, double gamma, int bc, int dtype, mhd_t** out)
+{
+    g_err.clear();
+    if (!out) return fail(MHD_ERR_ARG, "null output pointer");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(MHD_ERR_ARG, "grid sizes must be >= 1");
+    if ((long long)nx * ny * nz > (1LL << 40)) return fail(MHD_ERR_ARG, "grid too large");
+    if (!(gamma > 1.0) || !std::isfinite(gamma)) return fail(MHD_ERR_ARG, "gamma must be a finite number > 1");
+    if (bc != MHD_BC_PERIODIC && bc != MHD_BC_OUTFLOW) return fail(MHD_ERR_ARG, "unknown boundary condition");
+    if (dtype != MHD_F32 && dtype != MHD_F64) return fail(MHD_ERR_ARG, "unknown dtype");
+    mhd_solver* h = new (std::nothrow) mhd_solver();
+    if (!h) return fail(MHD_ERR_OOM, "host allocation failed");
+    h->g.n[0] = nx;
+    h->g.n[1] = ny;
+    h->g.n[2] = nz;
+    h->g.bc = bc;
+    h->g.N = (long long)nx * ny * nz;
+    h->gamma = gamma;
+    h->dtype = dtype;
+    h->esize = dtype == MHD_F64 ? 8 : 4;
+    h->stream = nullptr;
+    h->s = 0;
+    h->timing = false;
+    for (int k = 0; k < MHD_K_COUNT; k++) {
+        h->total_ms[k] = 0.0;
+        h->launches[k] = 0;
+    }
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hipGetDevice");
+    }
+    const size_t N = (size_t)h->g.N;
+    void* mem[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    const size_t sizes[5] = {5 * N * h->esize, 5 * N * h->esize, 3 * N * h->esize, 3 * N * h->esize, sizeof(Ctl)};
+    for (int k = 0; k < 5; k++) {
+        e = hipMalloc(&mem[k], sizes[k]);
+        if (e != hipSuccess) {
+            for (int q = 0; q < k; q++) (void)hipFree(mem[q]);
+            delete h;
+            (void)hipGetLastError();
+            return e == hipErrorOutOfMemory ? fail(MHD_ERR_OOM, "device allocation failed")
+                                            : hip_fail(e, "hipMalloc");
+        }
+    }
+    h->u[0] = mem[0];
+    h->u[1] = mem[1];
+    h->b[0] = mem[2];
+    h->b[1] = mem[3];
+    h->ctl = static_cast<Ctl*>(mem[4]);
+    h->ucur = h->bcur = 0;
+    Ctl c0;
+    std::memset(&c0, 0, sizeof(c0));
+    c0.t_stop = -1.0;
+    e = hipMemcpy(h->ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        for (int q = 0; q < 5; q++) (void)hipFree(mem[q]);
+        delete h;
+        return hip_fail(e, "init control block");
+    }
+    *out = h;
+    return MHD_OK;
+}
+
+int mhd_destroy(mhd_t* h)
+{
+    if (!h) return MHD_OK;
+    (void)set_current(h);
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(h->u[0]);
+    (void)hipFree(h->u[1]);
+    (void)hipFree(h->b[0]);
+    (void)hipFree(h->b[1]);
+    (void)hipFree(h->ctl);
+    for (int k = 0; k < MHD_K_COUNT; k++)
+        for (auto& pr : h->pending[k]) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
+    delete h;
+    return MHD_OK;
+}
+
+int mhd_set_stream(mhd_t* h, void* stream)
+{
+    if (int rc = check(h)) return rc;
+    h->stream = static_cast<hipStream_t>(stream);
+    return MHD_OK;
+}
+
+static int reset_time(mhd_t* h)
+{
+    Ctl c;
+    if (int rc = read_ctl(h, &c)) return rc;
+    c.t = 0.0;
+    c.dt = 0.0;
+    c.status = 0;
+    c.max_bits = 0;
+    c.blocks_done = 0;
+    c.div_bits = 0;
+    c.div_blocks_done = 0;
+    HIPCHK(hipMemcpyAsync(h->ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream), "write control block");
+    HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
+    h->s = 0;
+    return MHD_OK;
+}
+
+static int copy_in(mhd_t* h, const void* src, hipMemcpyKind kind)
+{
+    const size_t N = (size_t)h->g.N, es = h->esize;
+    const char* p = static_cast<const char*>(src);
+    h->ucur = h->bcur = 0;
+    HIPCHK(hipMemcpyAsync(h->u[0], p, 5 * N * es, kind, h->stream), "state copy in");
+    HIPCHK(hipMemcpyAsync(h->b[0], p + 5 * N * es, 3 * N * es, kind, h->stream), "state copy in");
+    return MHD_OK;
+}
+
+static int copy_out(mhd_t* h, void* dst, hipMemcpyKind kind)
+{
+    const size_t N = (size_t)h->g.N, es = h->esize;
+    char* p = static_cast<char*>(dst);
+    HIPCHK(hipMemcpyAsync(p, h->u[h->ucur], 5 * N * es, kind, h->stream), "state copy out");
+    HIPCHK(hipMemcpyAsync(p + 5 * N * es, h->b[h->bcur], 3 * N * es, kind, h->stream), "state copy out");
+    return MHD_OK;
+}
+
+int mhd_set_state(mhd_t* h, const void* host_state)
+{
+    if (int rc = check(h)) return rc;
+    if (!host_state) return fail(MHD_ERR_ARG, "null state pointer");
+    if (int rc = set_current(h)) return rc;
+    if (int rc = copy_in(h, host_state, hipMemcpyHostToDevice)) return rc;
+    return reset_time(h);
+}
+
+int mhd_set_state_device(mhd_t* h, const void* dev_state)
+{
+    if (int rc = check(h)) return rc;
+    if (!dev_state) return fail(MHD_ERR_ARG, "null state pointer");
+    if (int rc = set_current(h)) return rc;
+    if (int rc = copy_in(h, dev_state, hipMemcpyDeviceToDevice)) return rc;
+    return reset_time(h);
+}
+
+int mhd_get_state(mhd_t* h, void* host_state)
+{
+    if (int rc = check(h)) return rc;
+    if (!host_state) return fail(MHD_ERR_ARG, "null state pointer");
+    if (int rc = set_current(h)) return rc;
+    if (int rc = copy_out(h, host_state, hipMemcpyDeviceToHost)) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
+    return MHD_OK;
+}
+
+int mhd_get_state_device(mhd_t* h, void* dev_state)
+{
+    if (int rc = check(h)) return rc;
+    if (!dev_state) return fail(MHD_ERR_ARG, "null state pointer");
+    if (int rc = set_current(h)) return rc;
+    return copy_out(h, dev_state, hipMemcpyDeviceToDevice);
+}
+
+int mhd_step(mhd_t* h, int n, double cfl)
+{
+    if (int rc = check(h)) return rc;
+    if (n < 0) return fail(MHD_ERR_ARG, "negative step count");
+    if (!(cfl > 0.0 && cfl <= 1.0)) return fail(MHD_ERR_ARG, "cfl must be in (0, 1]");
+    if (int rc = set_current(h)) return rc;
+    int rc = h->dtype == MHD_F64 ? full_steps<double>(h, n, cfl) : full_steps<float>(h, n, cfl);
+    if (rc) return rc;
+    int status = 0;
+    HIPCHK(hipMemcpyAsync(&status, &h->ctl->status, sizeof(int), hipMemcpyDeviceToHost, h->stream), "read status");
+    HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
+    if (status != 0) return fail(MHD_ERR_NONFINITE, "non-finite or non-positive c_max; state frozen");
+    return MHD_OK;
+}
+
+int mhd_divb_max(mhd_t* h, double* out)
+{
+    if (int rc = check(h)) return rc;
+    if (!out) return fail(MHD_ERR_ARG, "null output pointer");
+    if (int rc = set_current(h)) return rc;
+    hipError_t e = h->dtype == MHD_F64
+                       ? mhd::launch_divb<double>(static_cast<const double*>(h->b[h->bcur]), h->g, h->ctl, h->stream)
+                       : mhd::launch_divb<float>(static_cast<const float*>(h->b[h->bcur]), h->g, h->ctl, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "div B launch");
+    Ctl c;
+    if (int rc = read_ctl(h, &c)) return rc;
+    *out = c.cmax;
+    return MHD_OK;
+}
+
+int mhd_cmax(mhd_t* h, double* out)
+{
+    if (int rc = check(h)) return rc;
+    if (!out) return fail(MHD_ERR_ARG, "null output pointer");
+    if (int rc = set_current(h)) return rc;
+    hipError_t e =
+        h->dtype == MHD_F64
+            ? mhd::launch_cmax_only<double>(static_cast<const double*>(h->u[h->ucur]),
+                                            static_cast<const double*>(h->b[h->bcur]), h->g, h->gamma, h->ctl,
+                                            h->stream)
+            : mhd::launch_cmax_only<float>(static_cast<const float*>(h->u[h->ucur]),
+                                           static_cast<const float*>(h->b[h->bcur]), h->g, h->gamma, h->ctl,
+                                           h->stream);
+    if (e != hipSuccess) return hip_fail(e, "cmax launch");
+    Ctl c;
+    if (int rc = read_ctl(h, &c)) return rc;
+    *out = c.cmax;
+    return MHD_OK;
+}
+
+int mhd_get_time(mhd_t* h, double* t, int64_t* s)
+{
+    if (int rc = check(h)) return rc;
+    if (int rc = set_current(h)) return rc;
+    Ctl c;
+    if (int rc = read_ctl(h, &c)) return rc;
+    if (t) *t = c.t;
+    if (s) *s = h->s;
+    return MHD_OK;
+}
+
+int mhd_set_time(mhd_t* h, double t, int64_t s)
+{
+    if (int rc = check(h)) return rc;
+    if (!std::isfinite(t) || s < 0) return fail(MHD_ERR_ARG, "time must be finite and s >= 0");
+    if (int rc = set_current(h)) return rc;
+    HIPCHK(hipMemcpyAsync(&h->ctl->t, &t, sizeof(double), hipMemcpyHostToDevice, h->stream), "write time");
+    HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
+    h->s = s;
+    return MHD_OK;
+}
+
+int mhd_set_stop_time(mhd_t* h, double t_stop)
+{
+    if (int rc = check(h)) return rc;
+    if (std::isnan(t_stop)) return fail(MHD_ERR_ARG, "stop time is NaN");
+    if (int rc = set_current(h)) return rc;
+    const double v = t_stop < 0.0 ? -1.0 : t_stop;
+    HIPCHK(hipMemcpyAsync(&h->ctl->t_stop, &v, sizeof(double), hipMemcpyHostToDevice, h->stream), "write stop time");
+    HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
+    return MHD_OK;
+}
+
+int mhd_fluid_sweep(mhd_t* h, int axis, double dt)
+{
+    if (int rc = check(h)) return rc;
+    if (axis < 0 || axis > 2) return fail(MHD_ERR_ARG, "axis must be 0, 1 or 2");
+    if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(MHD_ERR_ARG, "dt must be finite and >= 0");
+    if (int rc = set_current(h)) return rc;
+    return h->dtype == MHD_F64 ? fluid<double>(h, axis, dt) : fluid<float>(h, axis, dt);
+}
+
+int mhd_ct_sweep(mhd_t* h, int axis, double dt)
+{
+    if (int rc = check(h)) return rc;
+    if (axis < 0 || axis > 2) return fail(MHD_ERR_ARG, "axis must be 0, 1 or 2");
+    if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(MHD_ERR_ARG, "dt must be finite and >= 0");
+    if (int rc = set_current(h)) return rc;
+    return h->dtype == MHD_F64 ? ct<double>(h, axis, dt) : ct<float>(h, axis, dt);
+}
+
+int mhd_step_dt(mhd_t* h, double dt, int64_t s_order)
+{
+    if (int rc = check(h)) return rc;
+    if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(MHD_ERR_ARG, "dt must be finite and >= 0");
+    if (s_order < 0) return fail(MHD_ERR_ARG, "sweep-order index must be >= 0");
+    if (int rc = set_current(h)) return rc;
+    return h->dtype == MHD_F64 ? sweeps<double>(h, s_order, dt) : sweeps<float>(h, s_order, dt);
+}
+
+static int collect_timing(mhd_t* h)
+{
+    HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
+    for (int k = 0; k < MHD_K_COUNT; k++) {
+        for (auto& pr : h->pending[k]) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second), "hipEventElapsedTime");
+            h->total_ms[k] += ms;
+            h->launches[k] += 1;
+            h->pool.push_back(pr.first);
+            h->pool.push_back(pr.second);
+        }
+        h->pending[k].clear();
+    }
+    return MHD_OK;
+}
+
+int mhd_timing(mhd_t* h, int enable)
+{
+    if (int rc = check(h)) return rc;
+    if (int rc = set_current(h)) return rc;
+    if (int rc = collect_timing(h)) return rc;
+    if (enable) {
+        for (int k = 0; k < MHD_K_COUNT; k++) {
+            h->total_ms[k] = 0.0;
+            h->launches[k] = 0;
+        }
+    }
+    h->timing = enable != 0;
+    return MHD_OK;
+}
+
+int mhd_timing_read(mhd_t* h, int kind, double* total_ms, int64_t* launches)
+{
+    if (int rc = check(h)) return rc;
+    if (kind < 0 || kind >= MHD_K_COUNT) return fail(MHD_ERR_ARG, "unknown kernel kind");
+    if (int rc = set_current(h)) return rc;
+    if (int rc = collect_timing(h)) return rc;
+    if (total_ms) *total_ms = h->total_ms[kind];
+    if (launches) *launches = h->launches[kind];
+    return MHD_OK;
+}
+
+}  // extern "C"

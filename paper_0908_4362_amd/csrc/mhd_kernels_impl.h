@@ -1,0 +1,965 @@
+// HIP kernels (gfx950) of one time step of the relaxing-TVD + constrained-
+// transport ideal-MHD scheme (Wong et al., Sec. 3 and Sec. 4.3).
+//
+// Data layout: conserved fields u = (rho, m_x, m_y, m_z, E) and face fields
+// b = (B_x, B_y, B_z), each field x-fastest with N = nx*ny*nz cells; B_d(c)
+// sits on the lower d-face of cell c (eq. equat_b). Every sweep is
+// out-of-place (ping-pong buffers), so no workgroup ever reads a value that
+// another workgroup of the same launch writes.
+//
+// Boundaries: every read beyond the grid goes through the per-axis index map
+// (periodic wrap or outflow clamp) of the primary state; derived quantities
+// beyond the edge are recomputed from mapped primary values, never wrapped.
+//
+// Sweeps along y and z march through each pencil: a thread owns one x column
+// (64 consecutive x per wavefront, so every load and store is coalesced) and
+// walks along the sweep axis keeping the stencil window in registers; a pencil
+// is cut into chunks that re-run a short warm-up. Sweeps along x stage one
+// pencil segment per workgroup in LDS, one cell per thread.
+#pragma once
+#include <type_traits>
+
+#include "mhd_internal.h"
+
+namespace mhd {
+namespace {
+
+// FP64 instantiations are compiled without FMA contraction and evaluate every
+// expression in the same order, with the same divisions, as the CPU oracle,
+// so the double-precision path reproduces it bit for bit (the upwind choice of
+// the field update is discontinuous at exact ties, which symmetric problems
+// produce, so only identical arithmetic makes both take the same branch).
+// FP32 instantiations use FMA and one reciprocal of rho per cell.
+template <typename T>
+constexpr bool kExact = std::is_same<T, double>::value;
+
+constexpr int GF = 3;  // ghost depth of the fluid sweep
+constexpr int GB = 4;  // ghost depth of the field (CT) sweep
+
+__device__ __forceinline__ int wrap_idx(int i, int n, int bc)
+{
+    if ((unsigned)i < (unsigned)n) return i;
+    if (bc == 0) {
+        int r = i % n;
+        return r < 0 ? r + n : r;
+    }
+    return i < 0 ? 0 : n - 1;
+}
+
+template <typename T>
+__device__ __forceinline__ T vanleer(T a, T b)
+{
+    // eq. limiter; zero when the half-differences differ in sign
+    const T ab = a * b;
+    return ab > T(0) ? T(2) * ab / (a + b) : T(0);
+}
+
+// Movers r = (c u + F)/2 and l = (c u - F)/2 of eq. lr (times c) for a cell
+// with conserved u (normal momentum second) and centred field b (normal
+// first); F is eq. flux rotated to the sweep axis, c = |v_n| + sqrt(|gamma p +
+// B^2| / rho) the per-cell freezing speed.
+template <typename T>
+__device__ __forceinline__ void movers(const T* u, const T* b, T gamma, T* r, T* l)
+{
+    T F[5], c;
+    if constexpr (kExact<T>) {
+        const T rho = u[0];
+        const T vn = u[1] / rho, v1 = u[2] / rho, v2 = u[3] / rho;
+        const T bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+        const T vv = vn * vn + v1 * v1 + v2 * v2;
+        const T p = (gamma - T(1)) * (u[4] - T(0.5) * rho * vv - T(0.5) * bb);
+        const T ps = p + T(0.5) * bb;
+        const T bv = b[0] * vn + b[1] * v1 + b[2] * v2;
+        F[0] = u[1];
+        F[1] = u[1] * vn + ps - b[0] * b[0];
+        F[2] = u[2] * vn - b[0] * b[1];
+        F[3] = u[3] * vn - b[0] * b[2];
+        F[4] = (u[4] + ps) * vn - b[0] * bv;
+        c = fabs(vn) + sqrt(fabs(gamma * p + bb) / rho);
+    } else {
+        const T rinv = T(1) / u[0];
+        const T vn = u[1] * rinv, v1 = u[2] * rinv, v2 = u[3] * rinv;
+        const T bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+        const T ke = T(0.5) * (u[1] * vn + u[2] * v1 + u[3] * v2);
+        const T p = (gamma - T(1)) * (u[4] - ke - T(0.5) * bb);
+        const T ps = p + T(0.5) * bb;
+        const T bv = b[0] * vn + b[1] * v1 + b[2] * v2;
+        F[0] = u[1];
+        F[1] = u[1] * vn + ps - b[0] * b[0];
+        F[2] = u[2] * vn - b[0] * b[1];
+        F[3] = u[3] * vn - b[0] * b[2];
+        F[4] = (u[4] + ps) * vn - b[0] * bv;
+        c = fabs(vn) + sqrt(fabs(gamma * p + bb) * rinv);
+    }
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+        r[q] = T(0.5) * (c * u[q] + F[q]);
+        l[q] = T(0.5) * (c * u[q] - F[q]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Register pipeline of the fluid sweep. push() consumes the conserved state
+// and centred field of the head cell h and returns the updated state of cell
+// h - 3 (valid once the window is full).
+template <typename T>
+struct FluidPipe {
+    T r1[5];          // r at h-1
+    T f1[5];          // first-order flux at (h-1) - 1/2
+    T u1[5], u2[5], u3[5];
+    T b1[3];          // centred field at h-1
+    T rp2[5], rp3[5], lp2[5], lp3[5];  // movers of u^{t+dt/2} at h-2, h-3
+    T R3[5];          // limited right mover at h-3
+    T f2[5];          // second-order flux at (h-3) - 1/2
+
+    __device__ __forceinline__ void clear()
+    {
+#pragma unroll
+        for (int q = 0; q < 5; q++) {
+            r1[q] = f1[q] = u1[q] = u2[q] = u3[q] = T(0);
+            rp2[q] = rp3[q] = lp2[q] = lp3[q] = R3[q] = f2[q] = T(0);
+        }
+        b1[0] = b1[1] = b1[2] = T(0);
+    }
+
+    __device__ __forceinline__ void push(const T* uh, const T* bh, T gamma, T dt, T* unew)
+    {
+        T rh[5], lh[5];
+        movers(uh, bh, gamma, rh, lh);
+        // stage 1 (eq. Delta_u_half): first-order upwind flux r_{h-1} - l_h at
+        // face h - 1/2, half step of cell h-1
+        T fh[5], uhalf[5];
+#pragma unroll
+        for (int q = 0; q < 5; q++) {
+            fh[q] = r1[q] - lh[q];
+            uhalf[q] = u1[q] - (dt * T(0.5)) * (fh[q] - f1[q]);
+        }
+        // stage 2 (Alg. 1 step 7, eq. Delta_u_full): movers of u^{t+dt/2} at
+        // h-1 with the same field, van Leer limited slopes at h-2
+        T rp1[5], lp1[5];
+        movers(uhalf, b1, gamma, rp1, lp1);
+        T R2[5];
+#pragma unroll
+        for (int q = 0; q < 5; q++) {
+            const T sr = vanleer((rp2[q] - rp3[q]) / T(2), (rp1[q] - rp2[q]) / T(2));
+            const T sl = vanleer((lp2[q] - lp3[q]) / T(2), (lp1[q] - lp2[q]) / T(2));
+            R2[q] = rp2[q] + sr;
+            const T L2 = lp2[q] - sl;
+            // flux at (h-3) + 1/2: right mover from h-3, left mover from h-2
+            const T f = R3[q] - L2;
+            unew[q] = u3[q] - dt * (f - f2[q]);
+            f2[q] = f;
+        }
+#pragma unroll
+        for (int q = 0; q < 5; q++) {
+            R3[q] = R2[q];
+            rp3[q] = rp2[q];
+            rp2[q] = rp1[q];
+            lp3[q] = lp2[q];
+            lp2[q] = lp1[q];
+            f1[q] = fh[q];
+            r1[q] = rh[q];
+            u3[q] = u2[q];
+            u2[q] = u1[q];
+            u1[q] = uh[q];
+        }
+        b1[0] = bh[0];
+        b1[1] = bh[1];
+        b1[2] = bh[2];
+    }
+};
+
+// Register pipeline of one EMF along the sweep (Alg. 2 steps 4-8). push()
+// consumes the raw face velocity and face field of head h and returns the
+// limited upwind EMF at edge (h-4) + 1/2.
+template <typename T>
+struct EmfPipe {
+    T vh1, vh2;       // raw face velocity at h-1, h-2
+    T v2;             // smoothed velocity at h-2
+    T B1, B2, B3, B4; // face field at h-1 .. h-4
+    T q2;             // v B at h-2
+    T g3;             // first-order EMF at edge (h-3) + 1/2
+    T qh3, qh4;       // v B^{t+dt/2} at h-3, h-4
+    T s4;             // limited slope at h-4
+    T e3, e4;         // edge velocity at (h-3) + 1/2, (h-4) + 1/2
+    T G5;             // EMF at edge (h-5) + 1/2
+
+    __device__ __forceinline__ void clear()
+    {
+        vh1 = vh2 = v2 = B1 = B2 = B3 = B4 = q2 = g3 = qh3 = qh4 = s4 = e3 = e4 = G5 = T(0);
+    }
+
+    __device__ __forceinline__ T push(T vhat, T Bh, T dt)
+    {
+        // 1-2-1 smoothing along the sweep (eq. averaging_x) -> v at h-1
+        const T v1 = T(0.25) * (vh2 + T(2) * vh1 + vhat);
+        const T q1 = v1 * B1;
+        // edge velocity and first-order upwind EMF at (h-2) + 1/2 (eq. first_flux)
+        const T e2 = T(0.5) * (v2 + v1);
+        const T g2 = e2 > T(0) ? q2 : q1;
+        // half step of the advected component at h-2
+        const T bh2 = B2 - (dt * T(0.5)) * (g2 - g3);
+        const T qh2 = v2 * bh2;
+        // limited slope at h-3 and second-order EMF at (h-4) + 1/2
+        const T s3 = vanleer((qh3 - qh4) / T(2), (qh2 - qh3) / T(2));
+        const T G4 = e4 > T(0) ? qh4 + s4 : qh3 - s3;
+        e4 = e3;
+        e3 = e2;
+        s4 = s3;
+        qh4 = qh3;
+        qh3 = qh2;
+        g3 = g2;
+        q2 = q1;
+        B4 = B3;
+        B3 = B2;
+        B2 = B1;
+        B1 = Bh;
+        v2 = v1;
+        vh2 = vh1;
+        vh1 = vhat;
+        return G4;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// fluid_d for d = y (D = 1) or z (D = 2): marching kernel.
+// block (64, W): lanes along x, W wavefronts along the remaining axis TA;
+// grid (ceil(nx/64), ceil(n_TA/W), chunks along d).
+template <typename T, int D>
+__global__ void __launch_bounds__(256) fluid_march(const T* __restrict__ uin, T* __restrict__ uout,
+                                                   const T* __restrict__ bf, Grid g, T gamma,
+                                                   const Ctl* __restrict__ ctl, double dt_arg, int chunk)
+{
+    constexpr int E = (D + 1) % 3, F = (D + 2) % 3;
+    constexpr int TA = (D == 1) ? 2 : 1;
+    const int nx = g.n[0], nd = g.n[D], nt = g.n[TA];
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int tc = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= nx || tc >= nt) return;
+    const int o0 = blockIdx.z * chunk;
+    const int o1 = min(o0 + chunk, nd);
+    if (o0 >= o1) return;
+    const long long N = g.N;
+    const long long sd = (D == 1) ? (long long)nx : (long long)nx * g.n[1];
+    const long long st = (TA == 1) ? (long long)nx : (long long)nx * g.n[1];
+    const long long base = i + tc * st;
+    const long long xp = wrap_idx(i + 1, nx, g.bc) - i;
+    const long long tp = (long long)(wrap_idx(tc + 1, nt, g.bc) - tc) * st;
+    const long long offE = (E == 0) ? xp : tp;
+    const long long offF = (F == 0) ? xp : tp;
+    const T* rho = uin;
+    const T* mD = uin + (1 + D) * N;
+    const T* mE = uin + (1 + E) * N;
+    const T* mF = uin + (1 + F) * N;
+    const T* en = uin + 4 * N;
+    const T* BD = bf + D * N;
+    const T* BE = bf + E * N;
+    const T* BF = bf + F * N;
+    const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
+    const bool frozen = ctl->status != 0;
+
+    FluidPipe<T> P;
+    P.clear();
+    T bd_lo = BD[base + (long long)wrap_idx(o0 - GF, nd, g.bc) * sd];
+    for (int h = o0 - GF; h <= o1 + GF - 1; ++h) {
+        const long long c = base + (long long)wrap_idx(h, nd, g.bc) * sd;
+        const T bd_hi = BD[base + (long long)wrap_idx(h + 1, nd, g.bc) * sd];
+        T uh[5] = {rho[c], mD[c], mE[c], mF[c], en[c]};
+        T bh[3] = {T(0.5) * (bd_lo + bd_hi), T(0.5) * (BE[c] + BE[c + offE]), T(0.5) * (BF[c] + BF[c + offF])};
+        bd_lo = bd_hi;
+        const T keep[5] = {P.u3[0], P.u3[1], P.u3[2], P.u3[3], P.u3[4]};
+        T un[5];
+        P.push(uh, bh, gamma, dt, un);
+        const int o = h - GF;
+        if (o >= o0) {
+            const long long co = base + (long long)o * sd;
+            uout[co] = frozen ? keep[0] : un[0];
+            uout[(1 + D) * N + co] = frozen ? keep[1] : un[1];
+            uout[(1 + E) * N + co] = frozen ? keep[2] : un[2];
+            uout[(1 + F) * N + co] = frozen ? keep[3] : un[3];
+            uout[4 * N + co] = frozen ? keep[4] : un[4];
+        }
+    }
+}
+
+// B_{e->d}, B_{f->d} for d = y or z: marching kernel, same launch shape as
+// fluid_march. Each thread runs four EMF pipelines: the e- and f-face pencils
+// through its own cells and through the +e / +f neighbours (their EMFs enter
+// the constraint update of B_d).
+template <typename T, int D>
+__global__ void __launch_bounds__(256) ct_march(const T* __restrict__ uf, const T* __restrict__ bin,
+                                                T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
+                                                double dt_arg, int chunk)
+{
+    constexpr int E = (D + 1) % 3, F = (D + 2) % 3;
+    constexpr int TA = (D == 1) ? 2 : 1;
+    const int nx = g.n[0], nd = g.n[D], nt = g.n[TA];
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int tc = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= nx || tc >= nt) return;
+    const int o0 = blockIdx.z * chunk;
+    const int o1 = min(o0 + chunk, nd);
+    if (o0 >= o1) return;
+    const long long N = g.N;
+    const long long sd = (D == 1) ? (long long)nx : (long long)nx * g.n[1];
+    const long long st = (TA == 1) ? (long long)nx : (long long)nx * g.n[1];
+    const long long base = i + tc * st;
+    const long long xp = wrap_idx(i + 1, nx, g.bc) - i;
+    const long long xm = wrap_idx(i - 1, nx, g.bc) - i;
+    const long long tp = (long long)(wrap_idx(tc + 1, nt, g.bc) - tc) * st;
+    const long long tm = (long long)(wrap_idx(tc - 1, nt, g.bc) - tc) * st;
+    const long long offEp = (E == 0) ? xp : tp, offEm = (E == 0) ? xm : tm;
+    const long long offFp = (F == 0) ? xp : tp, offFm = (F == 0) ? xm : tm;
+    const T* rho = uf;
+    const T* md = uf + (1 + D) * N;
+    const T* BD = bin + D * N;
+    const T* BE = bin + E * N;
+    const T* BF = bin + F * N;
+    const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
+    const bool frozen = ctl->status != 0;
+
+    EmfPipe<T> e0, e1, f0, f1;
+    e0.clear();
+    e1.clear();
+    f0.clear();
+    f1.clear();
+    for (int h = o0 - GB; h <= o1 + GB - 1; ++h) {
+        const long long c = base + (long long)wrap_idx(h, nd, g.bc) * sd;
+        const T r0 = rho[c], m0 = md[c];
+        const T rEm = rho[c + offEm], mEm = md[c + offEm];
+        const T rEp = rho[c + offEp], mEp = md[c + offEp];
+        const T rFm = rho[c + offFm], mFm = md[c + offFm];
+        const T rFp = rho[c + offFp], mFp = md[c + offFp];
+        // original transverse faces of the output cell h - 4
+        const T be = e0.B4, bfv = f0.B4;
+        // face velocity along d on a transverse face: mass-weighted mean of the
+        // two cells sharing it (Alg. 2 step 4)
+        const T Ge0 = e0.push((mEm + m0) / (rEm + r0), BE[c], dt);
+        const T Ge1 = e1.push((m0 + mEp) / (r0 + rEp), BE[c + offEp], dt);
+        const T Gf0 = f0.push((mFm + m0) / (rFm + r0), BF[c], dt);
+        const T Gf1 = f1.push((m0 + mFp) / (r0 + rFp), BF[c + offFp], dt);
+        const int o = h - GB;
+        if (o >= o0) {
+            const long long co = base + (long long)o * sd;
+            // e0.G5 etc. still hold the EMFs at edge o - 1/2 (updated below)
+            const T bd = BD[co];
+            if (frozen) {
+                bout[E * N + co] = be;
+                bout[F * N + co] = bfv;
+                bout[D * N + co] = bd;
+            } else {
+                bout[E * N + co] = be - dt * (Ge0 - e0.G5);
+                bout[F * N + co] = bfv - dt * (Gf0 - f0.G5);
+                bout[D * N + co] = (bd + dt * (e1.G5 - e0.G5)) + dt * (f1.G5 - f0.G5);
+            }
+        }
+        e0.G5 = Ge0;
+        e1.G5 = Ge1;
+        f0.G5 = Gf0;
+        f1.G5 = Gf1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fluid_x: one workgroup stages R rows x (S + 6) cells in LDS, one cell per
+// thread per pass (at most two passes), and updates S cells per row.
+constexpr int XT = 256;   // threads per workgroup of the x kernels
+constexpr int XP = 2;     // passes (cells per thread)
+
+template <typename T>
+__global__ void __launch_bounds__(XT) fluid_x_lds(const T* __restrict__ uin, T* __restrict__ uout,
+                                                  const T* __restrict__ bf, Grid g, T gamma,
+                                                  const Ctl* __restrict__ ctl, double dt_arg, int S, int R)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sr = reinterpret_cast<T*>(smem_raw);
+    const int Ext = S + 2 * GF;
+    const int ncell = R * Ext;
+    T* sl = sr + 5 * ncell;
+    const int nx = g.n[0], ny = g.n[1];
+    const long long nrows = (long long)ny * g.n[2];
+    const long long N = g.N;
+    const int o0 = blockIdx.y * S;
+    const long long row0 = (long long)blockIdx.x * R;
+    const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
+    const bool frozen = ctl->status != 0;
+
+    T u[XP][5], b[XP][3], rr[XP][5], ll[XP][5];
+    int m_[XP], slot[XP];
+    long long cidx[XP];
+    bool act[XP];
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        const int idx = threadIdx.x + p * XT;
+        const int rl = idx / Ext;
+        const int m = idx - rl * Ext;
+        const long long row = row0 + rl;
+        act[p] = idx < ncell && row < nrows;
+        m_[p] = m;
+        slot[p] = idx;
+        cidx[p] = 0;
+        if (act[p]) {
+            const int j = (int)(row % ny);
+            const int k = (int)(row / ny);
+            const int x = wrap_idx(o0 - GF + m, nx, g.bc);
+            const int xn = wrap_idx(o0 - GF + m + 1, nx, g.bc);
+            const long long rb = (long long)nx * (j + (long long)ny * k);
+            const long long c = rb + x;
+            const long long cy = (long long)nx * (wrap_idx(j + 1, ny, g.bc) + (long long)ny * k) + x;
+            const long long cz = (long long)nx * (j + (long long)ny * wrap_idx(k + 1, g.n[2], g.bc)) + x;
+            cidx[p] = c;
+            u[p][0] = uin[c];
+            u[p][1] = uin[N + c];
+            u[p][2] = uin[2 * N + c];
+            u[p][3] = uin[3 * N + c];
+            u[p][4] = uin[4 * N + c];
+            b[p][0] = T(0.5) * (bf[c] + bf[rb + xn]);
+            b[p][1] = T(0.5) * (bf[N + c] + bf[N + cy]);
+            b[p][2] = T(0.5) * (bf[2 * N + c] + bf[2 * N + cz]);
+            movers(u[p], b[p], gamma, rr[p], ll[p]);
+#pragma unroll
+            for (int q = 0; q < 5; q++) {
+                sr[q * ncell + idx] = rr[p][q];
+                sl[q * ncell + idx] = ll[p][q];
+            }
+        }
+    }
+    __syncthreads();
+    // stage 1: half step of cells m in [1, Ext-1), movers of the half state
+    T rp[XP][5], lp[XP][5];
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        if (act[p] && m_[p] >= 1 && m_[p] < Ext - 1) {
+            const int s = slot[p];
+            T uh[5];
+#pragma unroll
+            for (int q = 0; q < 5; q++) {
+                const T fp = rr[p][q] - sl[q * ncell + s + 1];
+                const T fm = sr[q * ncell + s - 1] - ll[p][q];
+                uh[q] = u[p][q] - (dt * T(0.5)) * (fp - fm);
+            }
+            movers(uh, b[p], gamma, rp[p], lp[p]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        if (act[p] && m_[p] >= 1 && m_[p] < Ext - 1) {
+#pragma unroll
+            for (int q = 0; q < 5; q++) {
+                sr[q * ncell + slot[p]] = rp[p][q];
+                sl[q * ncell + slot[p]] = lp[p][q];
+            }
+        }
+    }
+    __syncthreads();
+    // stage 2: limited movers at cells m in [2, Ext-2)
+    T Rr[XP][5], Ll[XP][5];
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        if (act[p] && m_[p] >= 2 && m_[p] < Ext - 2) {
+            const int s = slot[p];
+#pragma unroll
+            for (int q = 0; q < 5; q++) {
+                const T a = sr[q * ncell + s - 1], c0 = rp[p][q], d = sr[q * ncell + s + 1];
+                Rr[p][q] = c0 + vanleer((c0 - a) / T(2), (d - c0) / T(2));
+                const T al = sl[q * ncell + s - 1], cl = lp[p][q], dl = sl[q * ncell + s + 1];
+                Ll[p][q] = cl - vanleer((cl - al) / T(2), (dl - cl) / T(2));
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        if (act[p] && m_[p] >= 2 && m_[p] < Ext - 2) {
+#pragma unroll
+            for (int q = 0; q < 5; q++) {
+                sr[q * ncell + slot[p]] = Rr[p][q];
+                sl[q * ncell + slot[p]] = Ll[p][q];
+            }
+        }
+    }
+    __syncthreads();
+    // full update of the S owned cells per row (eq. Delta_u_full)
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        const int m = m_[p];
+        const int x = o0 - GF + m;
+        if (act[p] && m >= GF && m < Ext - GF && x < nx) {
+            const int s = slot[p];
+            const long long c = cidx[p];
+#pragma unroll
+            for (int q = 0; q < 5; q++) {
+                const T fp = Rr[p][q] - sl[q * ncell + s + 1];
+                const T fm = sr[q * ncell + s - 1] - Ll[p][q];
+                uout[q * N + c] = frozen ? u[p][q] : u[p][q] - dt * (fp - fm);
+            }
+        }
+    }
+}
+
+// B_{y->x}, B_{z->x}: one workgroup stages R rows x (S + 8) cells in LDS and
+// runs the four EMF pencils of each row (own and +y for B_y, own and +z for
+// B_z) stage by stage.
+template <typename T>
+__global__ void __launch_bounds__(XT) ct_x_lds(const T* __restrict__ uf, const T* __restrict__ bin,
+                                               T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
+                                               double dt_arg, int S, int R)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sA = reinterpret_cast<T*>(smem_raw);   // 4 x ncell: velocities, then v B^{t+dt/2}
+    const int Ext = S + 2 * GB;
+    const int ncell = R * Ext;
+    T* sB = sA + 4 * ncell;                     // 4 x ncell: v B, then limited slopes
+    T* sC = sB + 4 * ncell;                     // 4 x ncell: first-order EMF, then EMF
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const long long nrows = (long long)ny * nz;
+    const long long N = g.N;
+    const int o0 = blockIdx.y * S;
+    const long long row0 = (long long)blockIdx.x * R;
+    const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
+    const bool frozen = ctl->status != 0;
+
+    // pencil p: 0 = B_y own, 1 = B_y at +y, 2 = B_z own, 3 = B_z at +z
+    T vh[XP][4], Bk[XP][4], vv[XP][4], ev[XP][4];
+    int m_[XP], slot[XP];
+    long long cidx[XP];
+    bool act[XP];
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        const int idx = threadIdx.x + p * XT;
+        const int rl = idx / Ext;
+        const int m = idx - rl * Ext;
+        const long long row = row0 + rl;
+        act[p] = idx < ncell && row < nrows;
+        m_[p] = m;
+        slot[p] = idx;
+        cidx[p] = 0;
+        if (act[p]) {
+            const int j = (int)(row % ny);
+            const int k = (int)(row / ny);
+            const int x = wrap_idx(o0 - GB + m, nx, g.bc);
+            const int jm = wrap_idx(j - 1, ny, g.bc), jp = wrap_idx(j + 1, ny, g.bc);
+            const int km = wrap_idx(k - 1, nz, g.bc), kp = wrap_idx(k + 1, nz, g.bc);
+            const long long c = (long long)nx * (j + (long long)ny * k) + x;
+            const long long cym = (long long)nx * (jm + (long long)ny * k) + x;
+            const long long cyp = (long long)nx * (jp + (long long)ny * k) + x;
+            const long long czm = (long long)nx * (j + (long long)ny * km) + x;
+            const long long czp = (long long)nx * (j + (long long)ny * kp) + x;
+            cidx[p] = c;
+            const T r0 = uf[c], m0 = uf[N + c];
+            vh[p][0] = (uf[N + cym] + m0) / (uf[cym] + r0);
+            vh[p][1] = (m0 + uf[N + cyp]) / (r0 + uf[cyp]);
+            vh[p][2] = (uf[N + czm] + m0) / (uf[czm] + r0);
+            vh[p][3] = (m0 + uf[N + czp]) / (r0 + uf[czp]);
+            Bk[p][0] = bin[N + c];
+            Bk[p][1] = bin[N + cyp];
+            Bk[p][2] = bin[2 * N + c];
+            Bk[p][3] = bin[2 * N + czp];
+#pragma unroll
+            for (int e = 0; e < 4; e++) sA[e * ncell + idx] = vh[p][e];
+        }
+    }
+    __syncthreads();
+    // smoothed velocity (eq. averaging_x) and v B at m in [1, Ext-1)
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        if (act[p] && m_[p] >= 1 && m_[p] < Ext - 1) {
+            const int s = slot[p];
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                vv[p][e] = T(0.25) * (sA[e * ncell + s - 1] + T(2) * vh[p][e] + sA[e * ncell + s + 1]);
+                sB[e * ncell + s] = vv[p][e] * Bk[p][e];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        if (act[p] && m_[p] >= 1 && m_[p] < Ext - 1) {
+#pragma unroll
+            for (int e = 0; e < 4; e++) sA[e * ncell + slot[p]] = vv[p][e];
+        }
+    }
+    __syncthreads();
+    // edge velocity and first-order upwind EMF at m + 1/2, m in [1, Ext-2)
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        if (act[p] && m_[p] >= 1 && m_[p] < Ext - 2) {
+            const int s = slot[p];
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                ev[p][e] = T(0.5) * (vv[p][e] + sA[e * ncell + s + 1]);
+                sC[e * ncell + s] = ev[p][e] > T(0) ? sB[e * ncell + s] : sB[e * ncell + s + 1];
+            }
+        }
+    }
+    __syncthreads();
+    // half step and v B^{t+dt/2} at m in [2, Ext-2)
+    T qh[XP][4];
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        if (act[p] && m_[p] >= 2 && m_[p] < Ext - 2) {
+            const int s = slot[p];
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const T bhalf = Bk[p][e] - (dt * T(0.5)) * (sC[e * ncell + s] - sC[e * ncell + s - 1]);
+                qh[p][e] = vv[p][e] * bhalf;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        if (act[p] && m_[p] >= 2 && m_[p] < Ext - 2) {
+#pragma unroll
+            for (int e = 0; e < 4; e++) sA[e * ncell + slot[p]] = qh[p][e];
+        }
+    }
+    __syncthreads();
+    // limited slopes at m in [3, Ext-3)
+    T sq[XP][4];
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        if (act[p] && m_[p] >= 3 && m_[p] < Ext - 3) {
+            const int s = slot[p];
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const T a = sA[e * ncell + s - 1], c0 = qh[p][e], d = sA[e * ncell + s + 1];
+                sq[p][e] = vanleer((c0 - a) / T(2), (d - c0) / T(2));
+                sB[e * ncell + s] = sq[p][e];
+            }
+        }
+    }
+    __syncthreads();
+    // second-order EMF at m + 1/2, m in [3, Ext-4)
+    T G[XP][4];
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        if (act[p] && m_[p] >= 3 && m_[p] < Ext - 4) {
+            const int s = slot[p];
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+                G[p][e] = ev[p][e] > T(0) ? qh[p][e] + sq[p][e] : sA[e * ncell + s + 1] - sB[e * ncell + s + 1];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        if (act[p] && m_[p] >= 3 && m_[p] < Ext - 4) {
+#pragma unroll
+            for (int e = 0; e < 4; e++) sC[e * ncell + slot[p]] = G[p][e];
+        }
+    }
+    __syncthreads();
+    // advection of B_y, B_z and constraint update of B_x for m in [4, Ext-4)
+#pragma unroll
+    for (int p = 0; p < XP; p++) {
+        const int m = m_[p];
+        const int x = o0 - GB + m;
+        if (act[p] && m >= GB && m < Ext - GB && x < nx) {
+            const int s = slot[p];
+            const long long c = cidx[p];
+            const T gm0 = sC[0 * ncell + s - 1], gm1 = sC[1 * ncell + s - 1];
+            const T gm2 = sC[2 * ncell + s - 1], gm3 = sC[3 * ncell + s - 1];
+            const T bx = bin[c];
+            if (frozen) {
+                bout[c] = bx;
+                bout[N + c] = Bk[p][0];
+                bout[2 * N + c] = Bk[p][2];
+            } else {
+                bout[N + c] = Bk[p][0] - dt * (G[p][0] - gm0);
+                bout[2 * N + c] = Bk[p][2] - dt * (G[p][2] - gm2);
+                bout[c] = (bx + dt * (gm1 - gm0)) + dt * (gm3 - gm2);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions: running max of non-negative values as ordered bit patterns
+// (NaN compares above every finite value and +inf, so it propagates).
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+template <int BS>
+__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v)
+{
+    __shared__ unsigned long long part[BS / 64];
+    v = wave_max_u64(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) part[w] = v;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        v = threadIdx.x < BS / 64 ? part[threadIdx.x] : 0ull;
+        v = wave_max_u64(v);
+    }
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long as_bits(double x)
+{
+    // non-negative or NaN inputs only; negative NaNs also sort above +inf
+    return (unsigned long long)__double_as_longlong(x);
+}
+
+constexpr int RB = 256;   // threads per block of the reductions
+
+// Per-cell CFL speed of eq. equat_CFL, global max, and (last block) the
+// time-step rule: dt = cfl / c_max, clipped so that t lands on t_stop.
+template <typename T, bool SETDT>
+__global__ void __launch_bounds__(RB) cfl_kernel(const T* __restrict__ u, const T* __restrict__ b, Grid g,
+                                                 T gamma, double cfl, Ctl* ctl)
+{
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const long long N = g.N;
+    unsigned long long best = 0ull;
+    // one x-row (j, k) per loop trip of a block, lanes along x: no integer division
+    const long long nrows = (long long)ny * nz;
+    for (long long row = blockIdx.x; row < nrows; row += gridDim.x) {
+      const int j = (int)(row % ny), k = (int)(row / ny);
+      const long long rb = row * nx;
+      const long long yoff = (long long)(wrap_idx(j + 1, ny, g.bc) - j) * nx;
+      const long long zoff = (long long)(wrap_idx(k + 1, nz, g.bc) - k) * nx * ny;
+      for (int i = threadIdx.x; i < nx; i += RB) {
+        const long long c = rb + i;
+        const long long cxp = rb + wrap_idx(i + 1, nx, g.bc);
+        const long long cyp = c + yoff;
+        const long long czp = c + zoff;
+        const T rho = u[c];
+        const T bx = T(0.5) * (b[c] + b[cxp]);
+        const T by = T(0.5) * (b[N + c] + b[N + cyp]);
+        const T bz = T(0.5) * (b[2 * N + c] + b[2 * N + czp]);
+        const T bb = bx * bx + by * by + bz * bz;
+        T cc;
+        if constexpr (kExact<T>) {
+            const T vx = u[N + c] / rho, vy = u[2 * N + c] / rho, vz = u[3 * N + c] / rho;
+            const T vv = vx * vx + vy * vy + vz * vz;
+            const T p = (gamma - T(1)) * (u[4 * N + c] - T(0.5) * rho * vv - T(0.5) * bb);
+            const T vm = fmax(fabs(vx), fmax(fabs(vy), fabs(vz)));
+            cc = vm + sqrt(fabs(gamma * p + bb) / rho);
+        } else {
+            const T rinv = T(1) / rho;
+            const T vx = u[N + c] * rinv, vy = u[2 * N + c] * rinv, vz = u[3 * N + c] * rinv;
+            const T ke = T(0.5) * (u[N + c] * vx + u[2 * N + c] * vy + u[3 * N + c] * vz);
+            const T p = (gamma - T(1)) * (u[4 * N + c] - ke - T(0.5) * bb);
+            const T vm = fmax(fabs(vx), fmax(fabs(vy), fabs(vz)));
+            cc = vm + sqrt(fabs(gamma * p + bb) * rinv);
+        }
+        if (cc != cc) cc = (T)__builtin_nan("");   // canonical positive NaN
+        const unsigned long long bits = as_bits((double)cc);
+        best = bits > best ? bits : best;
+      }
+    }
+    best = block_max_u64<RB>(best);
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
+        atomicMax(&ctl->max_bits, best);
+        __threadfence();
+        last = atomicAdd(&ctl->blocks_done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long mb = atomicMax(&ctl->max_bits, 0ull);
+        const double cmax = __longlong_as_double((long long)mb);
+        ctl->cmax = cmax;
+        ctl->max_bits = 0ull;
+        ctl->blocks_done = 0u;
+        if (SETDT) {
+            double dt = 0.0, t = ctl->t;
+            if (ctl->status == 0) {
+                if (!(cmax > 0.0) || cmax > 1.7976931348623157e308) {
+                    ctl->status = -4;
+                } else {
+                    double h = cfl / cmax;
+                    double tn = t + 2.0 * h;
+                    const double ts = ctl->t_stop;
+                    if (ts >= 0.0) {
+                        const double rem = ts - t;
+                        if (rem <= 0.0) {
+                            h = 0.0;
+                            tn = t;
+                        } else if (2.0 * h >= rem) {
+                            h = rem / 2.0;
+                            tn = ts;
+                        }
+                    }
+                    dt = h;
+                    t = tn;
+                }
+            }
+            ctl->dt = dt;
+            ctl->t = t;
+        }
+    }
+}
+
+// max over cells of |div B| (cells whose upper faces are stored)
+template <typename T>
+__global__ void __launch_bounds__(RB) divb_kernel(const T* __restrict__ b, Grid g, Ctl* ctl)
+{
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const long long N = g.N;
+    unsigned long long best = 0ull;
+    const long long nrows = (long long)ny * nz;
+    for (long long row = blockIdx.x; row < nrows; row += gridDim.x) {
+      const int j = (int)(row % ny), k = (int)(row / ny);
+      if (g.bc != 0 && ((ny > 1 && j == ny - 1) || (nz > 1 && k == nz - 1))) continue;
+      const long long rb = row * nx;
+      const long long yoff = (long long)(wrap_idx(j + 1, ny, g.bc) - j) * nx;
+      const long long zoff = (long long)(wrap_idx(k + 1, nz, g.bc) - k) * nx * ny;
+      for (int i = threadIdx.x; i < nx; i += RB) {
+        if (g.bc != 0 && nx > 1 && i == nx - 1) continue;
+        const long long c = rb + i;
+        const long long cxp = rb + wrap_idx(i + 1, nx, g.bc);
+        const long long cyp = c + yoff;
+        const long long czp = c + zoff;
+        double d = (double)(b[cxp] - b[c]);
+        d += (double)(b[N + cyp] - b[N + c]);
+        d += (double)(b[2 * N + czp] - b[2 * N + c]);
+        d = fabs(d);
+        if (d != d) d = __builtin_nan("");
+        const unsigned long long bits = as_bits(d);
+        best = bits > best ? bits : best;
+      }
+    }
+    best = block_max_u64<RB>(best);
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
+        atomicMax(&ctl->div_bits, best);
+        __threadfence();
+        last = atomicAdd(&ctl->div_blocks_done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long mb = atomicMax(&ctl->div_bits, 0ull);
+        ctl->cmax = __longlong_as_double((long long)mb);   // result slot read by the host
+        ctl->div_bits = 0ull;
+        ctl->div_blocks_done = 0u;
+    }
+}
+
+int reduce_blocks(const Grid& g)
+{
+    // one block per x-row (several rows per block on large grids)
+    long long b = (long long)g.n[1] * g.n[2];
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+// chunk length along the sweep for the marching kernels: enough workgroups to
+// fill the device, but long chunks to keep the warm-up share small
+int march_chunk(const Grid& g, int d, int ghost)
+{
+    const int ta = (d == 1) ? 2 : 1;
+    const long long waves = ((g.n[0] + 63) / 64) * (long long)g.n[ta];
+    const int nd = g.n[d];
+    long long want = 4096 / (waves > 0 ? waves : 1);
+    if (want < 1) want = 1;
+    int chunk = (int)((nd + want - 1) / want);
+    const int minchunk = 16 * ghost;
+    if (chunk < minchunk) chunk = minchunk;
+    if (chunk > nd) chunk = nd;
+    return chunk;
+}
+
+constexpr int MW = 4;   // wavefronts per marching workgroup
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_cfl(const T* u, const T* b, Grid g, double gamma, double cfl, Ctl* ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL((cfl_kernel<T, true>), dim3(reduce_blocks(g)), dim3(RB), 0, s, u, b, g, (T)gamma, cfl, ctl);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cmax_only(const T* u, const T* b, Grid g, double gamma, Ctl* ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL((cfl_kernel<T, false>), dim3(reduce_blocks(g)), dim3(RB), 0, s, u, b, g, (T)gamma, 0.0,
+                       ctl);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_divb(const T* b, Grid g, Ctl* ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL((divb_kernel<T>), dim3(reduce_blocks(g)), dim3(RB), 0, s, b, g, ctl);
+    return hipGetLastError();
+}
+
+template <typename T>
+static void x_tile(const Grid& g, int ghost, int& S, int& R)
+{
+    // one segment per row if it fits XT * XP cells, several rows per workgroup
+    // when rows are short
+    const int cap = XT * XP;
+    const int nx = g.n[0];
+    int nseg = 1;
+    while ((nx + nseg - 1) / nseg + 2 * ghost > cap) nseg++;
+    S = (nx + nseg - 1) / nseg;
+    R = cap / (S + 2 * ghost);
+    if (R < 1) R = 1;
+    const long long nrows = (long long)g.n[1] * g.n[2];
+    if (R > nrows) R = (int)nrows;
+}
+
+template <typename T>
+hipError_t launch_fluid(int axis, const T* u_in, T* u_out, const T* b, Grid g, double gamma, const Ctl* ctl,
+                        double dt, hipStream_t s)
+{
+    if (axis == 0) {
+        int S, R;
+        x_tile<T>(g, GF, S, R);
+        const long long nrows = (long long)g.n[1] * g.n[2];
+        dim3 grid((unsigned)((nrows + R - 1) / R), (g.n[0] + S - 1) / S);
+        const size_t lds = sizeof(T) * 10 * (size_t)R * (S + 2 * GF);
+        hipLaunchKernelGGL((fluid_x_lds<T>), grid, dim3(XT), lds, s, u_in, u_out, b, g, (T)gamma, ctl, dt, S, R);
+    } else {
+        const int chunk = march_chunk(g, axis, GF);
+        const int ta = (axis == 1) ? 2 : 1;
+        dim3 grid((g.n[0] + 63) / 64, (g.n[ta] + MW - 1) / MW, (g.n[axis] + chunk - 1) / chunk);
+        if (axis == 1)
+            hipLaunchKernelGGL((fluid_march<T, 1>), grid, dim3(64, MW), 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt, chunk);
+        else
+            hipLaunchKernelGGL((fluid_march<T, 2>), grid, dim3(64, MW), 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt, chunk);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ct(int axis, const T* u, const T* b_in, T* b_out, Grid g, const Ctl* ctl, double dt,
+                     hipStream_t s)
+{
+    if (axis == 0) {
+        int S, R;
+        x_tile<T>(g, GB, S, R);
+        const long long nrows = (long long)g.n[1] * g.n[2];
+        dim3 grid((unsigned)((nrows + R - 1) / R), (g.n[0] + S - 1) / S);
+        const size_t lds = sizeof(T) * 12 * (size_t)R * (S + 2 * GB);
+        hipLaunchKernelGGL((ct_x_lds<T>), grid, dim3(XT), lds, s, u, b_in, b_out, g, ctl, dt, S, R);
+    } else {
+        const int chunk = march_chunk(g, axis, GB);
+        const int ta = (axis == 1) ? 2 : 1;
+        dim3 grid((g.n[0] + 63) / 64, (g.n[ta] + MW - 1) / MW, (g.n[axis] + chunk - 1) / chunk);
+        if (axis == 1)
+            hipLaunchKernelGGL((ct_march<T, 1>), grid, dim3(64, MW), 0, s, u, b_in, b_out, g, ctl, dt, chunk);
+        else
+            hipLaunchKernelGGL((ct_march<T, 2>), grid, dim3(64, MW), 0, s, u, b_in, b_out, g, ctl, dt, chunk);
+    }
+    return hipGetLastError();
+}
+
+
+}  // namespace mhd

@@ -230,10 +230,12 @@ def random_smooth(nx, ny, nz, seed, gamma=5.0 / 3.0, amp=0.2, modes=3, bmean=(0.
             out = out + a * np.sin(k[0] * x + k[1] * y + k[2] * z + ph)
         return out
 
+    # at most one period per four cells along each axis (uniform along axes of < 4 cells)
+    kmax = [min(modes, n // 4) for n in (nx, ny, nz)]
+
     def draw():
-        return [(int(rng.integers(0, modes + 1)) if nx > 1 else 0,
-                 int(rng.integers(0, modes + 1)) if ny > 1 else 0,
-                 int(rng.integers(0, modes + 1)) if nz > 1 else 0,
+        return [(int(rng.integers(0, kmax[0] + 1)), int(rng.integers(0, kmax[1] + 1)),
+                 int(rng.integers(0, kmax[2] + 1)),
                  float(rng.uniform(-1, 1)), float(rng.uniform(0, 2 * math.pi))) for _ in range(4)]
 
     rho = 1.0 + amp * field(xc, yc, zc, draw())

@@ -1,0 +1,179 @@
+"""GPU checks of the C ABI semantics: round trips, resume, stop time, the
+non-finite guard, device-buffer entry points, the sub-operation entry points
+and the per-kernel timing."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_0908_4362_amd import problems as P
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0908_4362_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def note(msg):
+    print("[gpu] " + msg, flush=True)
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_round_trip_and_resume_bitwise(B, dtype):
+    nx, ny, nz = 33, 26, 20
+    s = P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 41)
+    note("round trip / resume dtype %d" % dtype)
+    with B.Solver(nx, ny, nz, H.GAMMA53, 0, dtype) as a:
+        a.set_state(s)
+        assert np.array_equal(a.get_state(), s.astype(a.np_dtype))
+        a.step(4)
+        mid = a.get_state()
+        t, st = a.time()
+        assert st == 4
+        a.step(4)
+        full = a.get_state()
+        t_full, _ = a.time()
+    with B.Solver(nx, ny, nz, H.GAMMA53, 0, dtype) as b:
+        b.set_state(mid)
+        B.mhd_set_time(b.h, t, st)
+        b.step(4)
+        assert np.array_equal(b.get_state(), full)
+        assert b.time() == (t_full, 8)
+    # the step counter selects the sweep order (s mod 3): resuming at s = 0
+    # instead of 4 takes other sweep orders and gives another result
+    with B.Solver(nx, ny, nz, H.GAMMA53, 0, dtype) as c:
+        c.set_state(mid)
+        c.step(4)
+        assert not np.array_equal(c.get_state(), full)
+
+
+def test_stop_time_lands_exactly_and_then_no_op(B):
+    s = P.brio_wu(128)
+    note("stop time")
+    with B.Solver(128, 1, 1, 2.0, 1, B.MHD_F64) as sv:
+        sv.set_state(s)
+        B.mhd_set_stop_time(sv.h, 5.5)
+        sv.step(200)
+        t, st = sv.time()
+        assert t == 5.5 and st == 200
+        a = sv.get_state()
+        sv.step(3)
+        assert np.array_equal(sv.get_state(), a)
+        B.mhd_set_stop_time(sv.h, None)
+        sv.step(1)
+        assert sv.time()[0] > 5.5
+
+
+def test_nonfinite_state_is_reported_and_frozen(B):
+    s = P.random_smooth(20, 18, 16, seed=P.MASTER_SEED + 42)
+    s[0, 3, 4, 5] = np.nan
+    note("nan guard")
+    with B.Solver(20, 18, 16, H.GAMMA53, 0, B.MHD_F64) as sv:
+        sv.set_state(s)
+        with pytest.raises(B.MHDError) as ei:
+            sv.step(2)
+        assert ei.value.code == B.MHD_ERR_NONFINITE
+        got = sv.get_state()
+        assert np.array_equal(got, s, equal_nan=True)
+        # still latched
+        with pytest.raises(B.MHDError):
+            sv.step(1)
+        # a fresh state clears it
+        s[0, 3, 4, 5] = 1.0
+        sv.set_state(s)
+        sv.step(1)
+    neg = P.random_smooth(20, 18, 16, seed=P.MASTER_SEED + 42)
+    neg[0] = -neg[0]
+    with B.Solver(20, 18, 16, H.GAMMA53, 0, B.MHD_F32) as sv:
+        sv.set_state(neg)
+        with pytest.raises(B.MHDError) as ei:
+            sv.step(1)
+        assert ei.value.code == B.MHD_ERR_NONFINITE
+
+
+def test_argument_errors(B):
+    with B.Solver(8, 8, 8, H.GAMMA53) as sv:
+        for bad in ((1, 0.0), (1, 1.5), (-1, 0.5), (1, float("nan"))):
+            with pytest.raises(B.MHDError) as ei:
+                B.mhd_step(sv.h, *bad)
+            assert ei.value.code == B.MHD_ERR_ARG
+        for fn in (B.mhd_fluid_sweep, B.mhd_ct_sweep):
+            with pytest.raises(B.MHDError):
+                fn(sv.h, 3, 0.1)
+            with pytest.raises(B.MHDError):
+                fn(sv.h, 0, -0.1)
+        with pytest.raises(B.MHDError):
+            B.mhd_set_time(sv.h, float("inf"), 0)
+        with pytest.raises(B.MHDError):
+            B.mhd_timing_read(sv.h, 9)
+
+
+def test_oversize_allocation_reports_oom(B):
+    with pytest.raises(B.MHDError) as ei:
+        B.mhd_create(4096, 4096, 2048, 1.4, 0, B.MHD_F64)   # 2.2 TB of state
+    assert ei.value.code in (B.MHD_ERR_OOM, B.MHD_ERR_DEVICE)
+
+
+def test_device_buffers_and_streams(B):
+    import torch
+
+    nx, ny, nz = 30, 22, 18
+    s = P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 43)
+    dev = torch.from_numpy(s).cuda()
+    out = torch.empty_like(dev)
+    stream = torch.cuda.Stream()
+    note("device buffers")
+    with B.Solver(nx, ny, nz, H.GAMMA53, 0, B.MHD_F64) as sv:
+        B.mhd_set_stream(sv.h, stream)
+        with torch.cuda.stream(stream):
+            B.mhd_set_state_device(sv.h, dev)
+            sv.step(2)
+            B.mhd_get_state_device(sv.h, out)
+        stream.synchronize()
+        host = sv.get_state()
+    with B.Solver(nx, ny, nz, H.GAMMA53, 0, B.MHD_F64) as ref:
+        ref.set_state(s)
+        ref.step(2)
+        want = ref.get_state()
+    assert np.array_equal(out.cpu().numpy(), want)
+    assert np.array_equal(host, want)
+
+
+def test_step_dt_matches_oracle(B, orc):
+    nx, ny, nz = 26, 21, 17
+    s = P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 44)
+    g = orc.Grid(nx, ny, nz, H.GAMMA53, 1)
+    note("step_dt")
+    with B.Solver(nx, ny, nz, H.GAMMA53, 1, B.MHD_F64) as sv:
+        sv.set_state(s)
+        for k in range(3):
+            B.mhd_step_dt(sv.h, 0.19, k + 5)
+        got = sv.get_state()
+        assert sv.time() == (0.0, 0)
+    want = s
+    for k in range(3):
+        want = orc.step_dt(g, want, 0.19, k + 5)
+    for f in range(8):
+        assert H.rel_linf(got[f], want[f]) <= 1e-11, f
+
+
+def test_timing_counts_launches(B):
+    with B.Solver(40, 30, 20, H.GAMMA53) as sv:
+        sv.set_state(P.random_smooth(40, 30, 20, seed=P.MASTER_SEED + 45))
+        B.mhd_timing(sv.h, True)
+        sv.step(3)
+        counts = [B.mhd_timing_read(sv.h, k)[1] for k in range(B.MHD_K_COUNT)]
+        ms = [B.mhd_timing_read(sv.h, k)[0] for k in range(B.MHD_K_COUNT)]
+        B.mhd_timing(sv.h, False)
+    assert counts == [3, 6, 6, 6, 6, 6, 6]
+    assert all(m > 0 for m in ms)
