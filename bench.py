@@ -69,7 +69,7 @@ def run_gpu(B, P, n, dtype, warmup, steps, stream):
 
 
 def roofline(kern, ncell, esize):
-    total = {k: v[0] for k, v in kern.items()}
+    total = {k: v[0] for k, v in kern.items() if v[1] > 0}
     dom = max(total, key=total.get)
     ms, cnt = kern[dom]
     avg_s = ms / cnt / 1e3

@@ -126,7 +126,7 @@ int mhd_step_dt(mhd_t* h, double dt, int64_t s_order);
 /* ---- per-kernel timing: HIP events recorded on the handle's stream around
  * every kernel launch, grouped by kind. ---- */
 enum {
-    MHD_K_CFL = 0,       /* max-speed reduction and dt rule                  */
+    MHD_K_CFL = 0,       /* max-speed reduction passes and dt rule           */
     MHD_K_FLUID_X = 1,   /* fluid_d, d = x, y, z: MHD_K_FLUID_X + d          */
     MHD_K_FLUID_Y = 2,
     MHD_K_FLUID_Z = 3,

@@ -1,10 +1,11 @@
 // Host runtime and C ABI of the MHD step library (declared in include/mhd.h).
 //
 // A handle owns two ping-pong copies of the conserved fields (5 x N) and of
-// the face fields (3 x N) plus a device control block holding dt, t, the stop
-// time, the reduction scratch and a latched status word. Every sweep reads one
-// copy and writes the other, so a full step (6 fluid and 6 field sweeps)
-// returns both to the copy it started from.
+// the face fields (3 x N), a device control block holding dt, t, the stop
+// time, c_max and a latched status word, and a small array of per-workgroup
+// maxima for the two-level reductions. Every sweep reads one copy and writes
+// the other, so a full step (6 fluid and 6 field sweeps) returns both to the
+// copy it started from.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -30,9 +31,13 @@ struct mhd_solver {
     void* b[2];           // face fields, ping-pong
     int ucur, bcur;       // current copies
     Ctl* ctl;             // device control block
+    unsigned long long* parts;  // per-workgroup maxima: [0, cap) c_max, [cap, 2 cap) div B
+    size_t cap;
+    int nparts;           // parts the last c_max producer wrote
     hipStream_t stream;
     long long s;          // step counter (host mirror; the sweep order needs it on the host)
     int device;
+    bool cmax_valid;      // parts hold the CFL maxima of the current state (from the last step)
     // optional per-kernel timing with HIP events on the handle's stream
     bool timing;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[MHD_K_COUNT];
@@ -95,13 +100,16 @@ int timed(mhd_solver* h, int kind, F&& f, const char* where)
 }
 
 template <typename T>
-int fluid(mhd_solver* h, int axis, double dt)
+int fluid(mhd_solver* h, int axis, double dt, bool with_cfl = false)
 {
     const T* uin = static_cast<const T*>(h->u[h->ucur]);
     T* uout = static_cast<T*>(h->u[h->ucur ^ 1]);
     const T* b = static_cast<const T*>(h->b[h->bcur]);
     int rc = timed(h, MHD_K_FLUID_X + axis,
-                   [&] { return mhd::launch_fluid<T>(axis, uin, uout, b, h->g, h->gamma, h->ctl, dt, h->stream); },
+                   [&] {
+                       return mhd::launch_fluid<T>(axis, uin, uout, b, h->g, h->gamma, h->ctl, dt,
+                                                   with_cfl ? h->parts : nullptr, &h->nparts, h->stream);
+                   },
                    "fluid sweep launch");
     if (rc) return rc;
     h->ucur ^= 1;
@@ -122,11 +130,13 @@ int ct(mhd_solver* h, int axis, double dt)
     return MHD_OK;
 }
 
-// The 12 sweeps of one full step with sweep-order index s (eq. L_sequence):
-// forward L_d = fluid_d then the field update along d; reverse L_d with the
-// field update first; axis order (x,y,z), (z,x,y), (y,z,x) by s mod 3.
+// The 12 sub-operations of one full step with sweep-order index s
+// (eq. L_sequence): forward L_d = fluid_d then the field update along d;
+// reverse L_d with the field update first; axis order (x,y,z), (z,x,y),
+// (y,z,x) by s mod 3. With reduce_cmax the last fluid sweep also stores the
+// per-workgroup maxima of the CFL speed of the state it writes.
 template <typename T>
-int sweeps(mhd_solver* h, long long s, double dt)
+int sweeps(mhd_solver* h, long long s, double dt, bool reduce_cmax)
 {
     static const int perm[3][3] = {{0, 1, 2}, {2, 0, 1}, {1, 2, 0}};
     const int* p = perm[((s % 3) + 3) % 3];
@@ -137,22 +147,38 @@ int sweeps(mhd_solver* h, long long s, double dt)
     }
     for (int a = 2; a >= 0; a--) {
         if ((rc = ct<T>(h, p[a], dt))) return rc;
-        if ((rc = fluid<T>(h, p[a], dt))) return rc;
+        if ((rc = fluid<T>(h, p[a], dt, reduce_cmax && a == 0))) return rc;
     }
     return MHD_OK;
 }
 
+// Per-workgroup CFL maxima of the current state into parts (standalone pass).
+template <typename T>
+int cfl_parts(mhd_solver* h)
+{
+    const T* u = static_cast<const T*>(h->u[h->ucur]);
+    const T* b = static_cast<const T*>(h->b[h->bcur]);
+    return timed(h, MHD_K_CFL,
+                 [&] { return mhd::launch_cfl<T>(u, b, h->g, h->gamma, h->parts, &h->nparts, h->stream); },
+                 "cfl launch");
+}
+
+// Full steps. The time-step rule runs on c_max of the current state; its
+// per-workgroup maxima come from the previous step's last fluid sweep, or from
+// a standalone pass after the state was replaced.
 template <typename T>
 int full_steps(mhd_solver* h, int n, double cfl)
 {
     for (int k = 0; k < n; k++) {
-        const T* u = static_cast<const T*>(h->u[h->ucur]);
-        const T* b = static_cast<const T*>(h->b[h->bcur]);
-        int rc = timed(h, MHD_K_CFL, [&] { return mhd::launch_cfl<T>(u, b, h->g, h->gamma, cfl, h->ctl, h->stream); },
-                       "cfl launch");
+        int rc;
+        if (!h->cmax_valid && (rc = cfl_parts<T>(h))) return rc;
+        rc = timed(h, MHD_K_CFL,
+                   [&] { return mhd::launch_finish(h->parts, h->nparts, 0, cfl, h->ctl, h->stream); },
+                   "dt launch");
         if (rc) return rc;
-        rc = sweeps<T>(h, h->s, -1.0);
+        rc = sweeps<T>(h, h->s, -1.0, true);
         if (rc) return rc;
+        h->cmax_valid = true;
         h->s += 1;
     }
     return MHD_OK;
@@ -189,7 +215,13 @@ size_t mhd_state_bytes(int nx, int ny, int nz, int dtype)
 {
     if (nx < 1 || ny < 1 || nz < 1 || (dtype != MHD_F32 && dtype != MHD_F64)) return 0;
     const size_t es = dtype == MHD_F64 ? 8 : 4;
-    return 2 * 8 * (size_t)nx * ny * nz * es + sizeof(Ctl);
+    mhd::Grid g;
+    g.n[0] = nx;
+    g.n[1] = ny;
+    g.n[2] = nz;
+    g.bc = 0;
+    g.N = (long long)nx * ny * nz;
+    return 2 * 8 * (size_t)g.N * es + sizeof(Ctl) + 2 * mhd::reduce_capacity(g) * sizeof(unsigned long long);
 }
 
 int mhd_create(int nx, int ny, int nz, double gamma, int bc, int dtype, mhd_t** out)
@@ -214,6 +246,7 @@ int mhd_create(int nx, int ny, int nz, double gamma, int bc, int dtype, mhd_t** 
     h->esize = dtype == MHD_F64 ? 8 : 4;
     h->stream = nullptr;
     h->s = 0;
+    h->cmax_valid = false;
     h->timing = false;
     for (int k = 0; k < MHD_K_COUNT; k++) {
         h->total_ms[k] = 0.0;
@@ -225,9 +258,12 @@ int mhd_create(int nx, int ny, int nz, double gamma, int bc, int dtype, mhd_t** 
         return hip_fail(e, "hipGetDevice");
     }
     const size_t N = (size_t)h->g.N;
-    void* mem[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    const size_t sizes[5] = {5 * N * h->esize, 5 * N * h->esize, 3 * N * h->esize, 3 * N * h->esize, sizeof(Ctl)};
-    for (int k = 0; k < 5; k++) {
+    h->cap = mhd::reduce_capacity(h->g);
+    h->nparts = 0;
+    void* mem[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    const size_t sizes[6] = {5 * N * h->esize, 5 * N * h->esize, 3 * N * h->esize, 3 * N * h->esize, sizeof(Ctl),
+                             2 * h->cap * sizeof(unsigned long long)};
+    for (int k = 0; k < 6; k++) {
         e = hipMalloc(&mem[k], sizes[k]);
         if (e != hipSuccess) {
             for (int q = 0; q < k; q++) (void)hipFree(mem[q]);
@@ -242,13 +278,14 @@ int mhd_create(int nx, int ny, int nz, double gamma, int bc, int dtype, mhd_t** 
     h->b[0] = mem[2];
     h->b[1] = mem[3];
     h->ctl = static_cast<Ctl*>(mem[4]);
+    h->parts = static_cast<unsigned long long*>(mem[5]);
     h->ucur = h->bcur = 0;
     Ctl c0;
     std::memset(&c0, 0, sizeof(c0));
     c0.t_stop = -1.0;
     e = hipMemcpy(h->ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        for (int q = 0; q < 5; q++) (void)hipFree(mem[q]);
+        for (int q = 0; q < 6; q++) (void)hipFree(mem[q]);
         delete h;
         return hip_fail(e, "init control block");
     }
@@ -266,6 +303,7 @@ int mhd_destroy(mhd_t* h)
     (void)hipFree(h->b[0]);
     (void)hipFree(h->b[1]);
     (void)hipFree(h->ctl);
+    (void)hipFree(h->parts);
     for (int k = 0; k < MHD_K_COUNT; k++)
         for (auto& pr : h->pending[k]) {
             (void)hipEventDestroy(pr.first);
@@ -290,10 +328,6 @@ static int reset_time(mhd_t* h)
     c.t = 0.0;
     c.dt = 0.0;
     c.status = 0;
-    c.max_bits = 0;
-    c.blocks_done = 0;
-    c.div_bits = 0;
-    c.div_blocks_done = 0;
     HIPCHK(hipMemcpyAsync(h->ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, h->stream), "write control block");
     HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
     h->s = 0;
@@ -305,6 +339,7 @@ static int copy_in(mhd_t* h, const void* src, hipMemcpyKind kind)
     const size_t N = (size_t)h->g.N, es = h->esize;
     const char* p = static_cast<const char*>(src);
     h->ucur = h->bcur = 0;
+    h->cmax_valid = false;
     HIPCHK(hipMemcpyAsync(h->u[0], p, 5 * N * es, kind, h->stream), "state copy in");
     HIPCHK(hipMemcpyAsync(h->b[0], p + 5 * N * es, 3 * N * es, kind, h->stream), "state copy in");
     return MHD_OK;
@@ -375,13 +410,18 @@ int mhd_divb_max(mhd_t* h, double* out)
     if (int rc = check(h)) return rc;
     if (!out) return fail(MHD_ERR_ARG, "null output pointer");
     if (int rc = set_current(h)) return rc;
+    unsigned long long* parts = h->parts + h->cap;
+    int np = 0;
     hipError_t e = h->dtype == MHD_F64
-                       ? mhd::launch_divb<double>(static_cast<const double*>(h->b[h->bcur]), h->g, h->ctl, h->stream)
-                       : mhd::launch_divb<float>(static_cast<const float*>(h->b[h->bcur]), h->g, h->ctl, h->stream);
+                       ? mhd::launch_divb<double>(static_cast<const double*>(h->b[h->bcur]), h->g, parts, &np,
+                                                  h->stream)
+                       : mhd::launch_divb<float>(static_cast<const float*>(h->b[h->bcur]), h->g, parts, &np,
+                                                 h->stream);
     if (e != hipSuccess) return hip_fail(e, "div B launch");
+    HIPCHK(mhd::launch_finish(parts, np, 1, 0.0, h->ctl, h->stream), "div B finish launch");
     Ctl c;
     if (int rc = read_ctl(h, &c)) return rc;
-    *out = c.cmax;
+    *out = c.divb;
     return MHD_OK;
 }
 
@@ -390,17 +430,12 @@ int mhd_cmax(mhd_t* h, double* out)
     if (int rc = check(h)) return rc;
     if (!out) return fail(MHD_ERR_ARG, "null output pointer");
     if (int rc = set_current(h)) return rc;
-    hipError_t e =
-        h->dtype == MHD_F64
-            ? mhd::launch_cmax_only<double>(static_cast<const double*>(h->u[h->ucur]),
-                                            static_cast<const double*>(h->b[h->bcur]), h->g, h->gamma, h->ctl,
-                                            h->stream)
-            : mhd::launch_cmax_only<float>(static_cast<const float*>(h->u[h->ucur]),
-                                           static_cast<const float*>(h->b[h->bcur]), h->g, h->gamma, h->ctl,
-                                           h->stream);
-    if (e != hipSuccess) return hip_fail(e, "cmax launch");
+    int rc = h->dtype == MHD_F64 ? cfl_parts<double>(h) : cfl_parts<float>(h);
+    if (rc) return rc;
+    HIPCHK(mhd::launch_finish(h->parts, h->nparts, 0, 0.0, h->ctl, h->stream), "cmax finish launch");
+    h->cmax_valid = true;
     Ctl c;
-    if (int rc = read_ctl(h, &c)) return rc;
+    if (int rc2 = read_ctl(h, &c)) return rc2;
     *out = c.cmax;
     return MHD_OK;
 }
@@ -444,6 +479,7 @@ int mhd_fluid_sweep(mhd_t* h, int axis, double dt)
     if (axis < 0 || axis > 2) return fail(MHD_ERR_ARG, "axis must be 0, 1 or 2");
     if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(MHD_ERR_ARG, "dt must be finite and >= 0");
     if (int rc = set_current(h)) return rc;
+    h->cmax_valid = false;
     return h->dtype == MHD_F64 ? fluid<double>(h, axis, dt) : fluid<float>(h, axis, dt);
 }
 
@@ -453,6 +489,7 @@ int mhd_ct_sweep(mhd_t* h, int axis, double dt)
     if (axis < 0 || axis > 2) return fail(MHD_ERR_ARG, "axis must be 0, 1 or 2");
     if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(MHD_ERR_ARG, "dt must be finite and >= 0");
     if (int rc = set_current(h)) return rc;
+    h->cmax_valid = false;
     return h->dtype == MHD_F64 ? ct<double>(h, axis, dt) : ct<float>(h, axis, dt);
 }
 
@@ -462,7 +499,8 @@ int mhd_step_dt(mhd_t* h, double dt, int64_t s_order)
     if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(MHD_ERR_ARG, "dt must be finite and >= 0");
     if (s_order < 0) return fail(MHD_ERR_ARG, "sweep-order index must be >= 0");
     if (int rc = set_current(h)) return rc;
-    return h->dtype == MHD_F64 ? sweeps<double>(h, s_order, dt) : sweeps<float>(h, s_order, dt);
+    h->cmax_valid = false;
+    return h->dtype == MHD_F64 ? sweeps<double>(h, s_order, dt, false) : sweeps<float>(h, s_order, dt, false);
 }
 
 static int collect_timing(mhd_t* h)

@@ -2,11 +2,11 @@
 #include "mhd_kernels_impl.h"
 
 namespace mhd {
-template hipError_t launch_cfl<float>(const float*, const float*, Grid, double, double, Ctl*, hipStream_t);
-template hipError_t launch_cmax_only<float>(const float*, const float*, Grid, double, Ctl*, hipStream_t);
-template hipError_t launch_divb<float>(const float*, Grid, Ctl*, hipStream_t);
+template hipError_t launch_cfl<float>(const float*, const float*, Grid, double, unsigned long long*, int*,
+                                      hipStream_t);
+template hipError_t launch_divb<float>(const float*, Grid, unsigned long long*, int*, hipStream_t);
 template hipError_t launch_fluid<float>(int, const float*, float*, const float*, Grid, double, const Ctl*, double,
-                                        hipStream_t);
+                                        unsigned long long*, int*, hipStream_t);
 template hipError_t launch_ct<float>(int, const float*, const float*, float*, Grid, const Ctl*, double,
                                      hipStream_t);
 }  // namespace mhd

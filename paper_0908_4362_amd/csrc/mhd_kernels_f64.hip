@@ -1,13 +1,55 @@
-// Double-precision instantiation of the step kernels. Built with
-// -ffp-contract=off: every FP64 expression rounds exactly as the CPU oracle's.
+// Double-precision instantiation of the step kernels, plus the
+// precision-independent launchers. Built with -ffp-contract=off: every FP64
+// expression rounds exactly as the CPU oracle's.
 #include "mhd_kernels_impl.h"
 
 namespace mhd {
-template hipError_t launch_cfl<double>(const double*, const double*, Grid, double, double, Ctl*, hipStream_t);
-template hipError_t launch_cmax_only<double>(const double*, const double*, Grid, double, Ctl*, hipStream_t);
-template hipError_t launch_divb<double>(const double*, Grid, Ctl*, hipStream_t);
+namespace {
+// Second level of a grid-wide max: one block reduces nparts per-block maxima;
+// what = 0: c_max into ctl->cmax, then (cfl > 0) the time-step rule;
+// what = 1: max |div B| into ctl->divb.
+constexpr int FB = 1024;   // threads of the finisher
+__global__ void __launch_bounds__(FB) finish_kernel(const unsigned long long* __restrict__ parts, int nparts,
+                                                    int what, double cfl, Ctl* ctl)
+{
+    unsigned long long best = 0ull;
+    for (int k = threadIdx.x; k < nparts; k += FB) best = parts[k] > best ? parts[k] : best;
+    best = block_max_u64<FB>(best, threadIdx.x);
+    if (threadIdx.x == 0) {
+        const double m = __longlong_as_double((long long)best);
+        if (what == 1) {
+            ctl->divb = m;
+        } else {
+            ctl->cmax = m;
+            if (cfl > 0.0) apply_dt_rule(ctl, cfl);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_finish(const unsigned long long* parts, int nparts, int what, double cfl, Ctl* ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(FB), 0, s, parts, nparts, what, cfl, ctl);
+    return hipGetLastError();
+}
+
+size_t reduce_capacity(const Grid& g)
+{
+    size_t cap = (size_t)reduce_blocks(g);
+    int S, R;
+    x_tile(g, GF, S, R);
+    cap = std::max(cap, (size_t)x_blocks(g, S, R));
+    for (int axis = 1; axis <= 2; axis++)
+        cap = std::max(cap, (size_t)march_blocks(g, axis, march_chunk(g, axis, GF)));
+    return cap;
+}
+
+template hipError_t launch_cfl<double>(const double*, const double*, Grid, double, unsigned long long*, int*,
+                                       hipStream_t);
+template hipError_t launch_divb<double>(const double*, Grid, unsigned long long*, int*, hipStream_t);
 template hipError_t launch_fluid<double>(int, const double*, double*, const double*, Grid, double, const Ctl*,
-                                         double, hipStream_t);
+                                         double, unsigned long long*, int*, hipStream_t);
 template hipError_t launch_ct<double>(int, const double*, const double*, double*, Grid, const Ctl*, double,
                                       hipStream_t);
 }  // namespace mhd

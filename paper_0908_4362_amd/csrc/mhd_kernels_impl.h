@@ -17,6 +17,7 @@
 // is cut into chunks that re-run a short warm-up. Sweeps along x stage one
 // pencil segment per workgroup in LDS, one cell per thread.
 #pragma once
+#include <algorithm>
 #include <type_traits>
 
 #include "mhd_internal.h"
@@ -52,6 +53,106 @@ __device__ __forceinline__ T vanleer(T a, T b)
     // eq. limiter; zero when the half-differences differ in sign
     const T ab = a * b;
     return ab > T(0) ? T(2) * ab / (a + b) : T(0);
+}
+
+// CFL speed of one cell, eq. equat_CFL: largest |v| component plus
+// sqrt(|gamma p + B^2| / rho); b is the centred field. FP64 follows the
+// oracle's expression order.
+template <typename T>
+__device__ __forceinline__ T cfl_speed(T rho, T mx, T my, T mz, T en, T bx, T by, T bz, T gamma)
+{
+    const T bb = bx * bx + by * by + bz * bz;
+    if constexpr (kExact<T>) {
+        const T vx = mx / rho, vy = my / rho, vz = mz / rho;
+        const T vv = vx * vx + vy * vy + vz * vz;
+        const T p = (gamma - T(1)) * (en - T(0.5) * rho * vv - T(0.5) * bb);
+        const T vm = fmax(fabs(vx), fmax(fabs(vy), fabs(vz)));
+        return vm + sqrt(fabs(gamma * p + bb) / rho);
+    } else {
+        const T rinv = T(1) / rho;
+        const T vx = mx * rinv, vy = my * rinv, vz = mz * rinv;
+        const T ke = T(0.5) * (mx * vx + my * vy + mz * vz);
+        const T p = (gamma - T(1)) * (en - ke - T(0.5) * bb);
+        const T vm = fmax(fabs(vx), fmax(fabs(vy), fabs(vz)));
+        return vm + sqrt(fabs(gamma * p + bb) * rinv);
+    }
+}
+
+// Ordered bit pattern of a non-negative value (NaN is mapped to the canonical
+// positive NaN, which sorts above +inf, so it propagates through a max).
+template <typename T>
+__device__ __forceinline__ unsigned long long speed_bits(T c)
+{
+    double d = (double)c;
+    if (d != d) d = __builtin_nan("");
+    return (unsigned long long)__double_as_longlong(d);
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Max over a block of BS threads (linear id tid); valid in thread 0.
+template <int BS>
+__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v, int tid)
+{
+    __shared__ unsigned long long part[BS / 64];
+    v = wave_max_u64(v);
+    if ((tid & 63) == 0) part[tid >> 6] = v;
+    __syncthreads();
+    if (tid < 64) {
+        v = tid < BS / 64 ? part[tid] : 0ull;
+        v = wave_max_u64(v);
+    }
+    return v;
+}
+
+// Grid-wide max, first level: every block stores its maximum in
+// parts[blockIdx.x] (plain stores, no atomics); a one-block finisher reduces
+// the parts.
+template <int BS>
+__device__ __forceinline__ void block_max_to_part(unsigned long long v, int tid, unsigned long long* parts)
+{
+    v = block_max_u64<BS>(v, tid);
+    if (tid == 0) parts[blockIdx.x] = v;
+}
+
+// Time-step rule (Sec. 4.2, eq. equat_CFL): dt = cfl / c_max, clipped so that
+// t + 2 dt lands exactly on the stop time, after which dt = 0; a NaN, infinite
+// or non-positive c_max latches the non-finite status.
+__device__ __forceinline__ void apply_dt_rule(Ctl* ctl, double cfl)
+{
+    const double cmax = ctl->cmax;
+    double dt = 0.0, t = ctl->t;
+    if (ctl->status == 0) {
+        if (!(cmax > 0.0) || cmax > 1.7976931348623157e308) {
+            ctl->status = -4;
+        } else {
+            double h = cfl / cmax;
+            double tn = t + 2.0 * h;
+            const double ts = ctl->t_stop;
+            if (ts >= 0.0) {
+                const double rem = ts - t;
+                if (rem <= 0.0) {
+                    h = 0.0;
+                    tn = t;
+                } else if (2.0 * h >= rem) {
+                    h = rem / 2.0;
+                    tn = ts;
+                }
+            }
+            dt = h;
+            t = tn;
+        }
+    }
+    ctl->dt = dt;
+    ctl->t = t;
 }
 
 // Movers r = (c u + F)/2 and l = (c u - F)/2 of eq. lr (times c) for a cell
@@ -106,8 +207,8 @@ template <typename T>
 struct FluidPipe {
     T r1[5];          // r at h-1
     T f1[5];          // first-order flux at (h-1) - 1/2
-    T u1[5], u2[5], u3[5];
-    T b1[3];          // centred field at h-1
+    T u1[5];          // conserved state at h-1
+    T b1[3], b2[3], b3[3];  // centred field at h-1, h-2, h-3
     T rp2[5], rp3[5], lp2[5], lp3[5];  // movers of u^{t+dt/2} at h-2, h-3
     T R3[5];          // limited right mover at h-3
     T f2[5];          // second-order flux at (h-3) - 1/2
@@ -116,13 +217,17 @@ struct FluidPipe {
     {
 #pragma unroll
         for (int q = 0; q < 5; q++) {
-            r1[q] = f1[q] = u1[q] = u2[q] = u3[q] = T(0);
+            r1[q] = f1[q] = u1[q] = T(0);
             rp2[q] = rp3[q] = lp2[q] = lp3[q] = R3[q] = f2[q] = T(0);
         }
         b1[0] = b1[1] = b1[2] = T(0);
+        b2[0] = b2[1] = b2[2] = T(0);
+        b3[0] = b3[1] = b3[2] = T(0);
     }
 
-    __device__ __forceinline__ void push(const T* uh, const T* bh, T gamma, T dt, T* unew)
+    // u3 is the state of the output cell h - 3 (re-read by the caller rather
+    // than carried, to keep the register window small).
+    __device__ __forceinline__ void push(const T* uh, const T* bh, T gamma, T dt, const T* u3, T* unew)
     {
         T rh[5], lh[5];
         movers(uh, bh, gamma, rh, lh);
@@ -159,13 +264,14 @@ struct FluidPipe {
             lp2[q] = lp1[q];
             f1[q] = fh[q];
             r1[q] = rh[q];
-            u3[q] = u2[q];
-            u2[q] = u1[q];
             u1[q] = uh[q];
         }
-        b1[0] = bh[0];
-        b1[1] = bh[1];
-        b1[2] = bh[2];
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            b3[q] = b2[q];
+            b2[q] = b1[q];
+            b1[q] = bh[q];
+        }
     }
 };
 
@@ -176,8 +282,7 @@ template <typename T>
 struct EmfPipe {
     T vh1, vh2;       // raw face velocity at h-1, h-2
     T v2;             // smoothed velocity at h-2
-    T B1, B2, B3, B4; // face field at h-1 .. h-4
-    T q2;             // v B at h-2
+    T B1, B2;         // face field at h-1, h-2
     T g3;             // first-order EMF at edge (h-3) + 1/2
     T qh3, qh4;       // v B^{t+dt/2} at h-3, h-4
     T s4;             // limited slope at h-4
@@ -186,7 +291,7 @@ struct EmfPipe {
 
     __device__ __forceinline__ void clear()
     {
-        vh1 = vh2 = v2 = B1 = B2 = B3 = B4 = q2 = g3 = qh3 = qh4 = s4 = e3 = e4 = G5 = T(0);
+        vh1 = vh2 = v2 = B1 = B2 = g3 = qh3 = qh4 = s4 = e3 = e4 = G5 = T(0);
     }
 
     __device__ __forceinline__ T push(T vhat, T Bh, T dt)
@@ -194,6 +299,7 @@ struct EmfPipe {
         // 1-2-1 smoothing along the sweep (eq. averaging_x) -> v at h-1
         const T v1 = T(0.25) * (vh2 + T(2) * vh1 + vhat);
         const T q1 = v1 * B1;
+        const T q2 = v2 * B2;
         // edge velocity and first-order upwind EMF at (h-2) + 1/2 (eq. first_flux)
         const T e2 = T(0.5) * (v2 + v1);
         const T g2 = e2 > T(0) ? q2 : q1;
@@ -209,9 +315,6 @@ struct EmfPipe {
         qh4 = qh3;
         qh3 = qh2;
         g3 = g2;
-        q2 = q1;
-        B4 = B3;
-        B3 = B2;
         B2 = B1;
         B1 = Bh;
         v2 = v1;
@@ -223,63 +326,111 @@ struct EmfPipe {
 
 // ---------------------------------------------------------------------------
 // fluid_d for d = y (D = 1) or z (D = 2): marching kernel.
-// block (64, W): lanes along x, W wavefronts along the remaining axis TA;
-// grid (ceil(nx/64), ceil(n_TA/W), chunks along d).
-template <typename T, int D>
-__global__ void __launch_bounds__(256) fluid_march(const T* __restrict__ uin, T* __restrict__ uout,
-                                                   const T* __restrict__ bf, Grid g, T gamma,
-                                                   const Ctl* __restrict__ ctl, double dt_arg, int chunk)
+// Block (64, MW): lanes along x, MW wavefronts along the remaining axis TA;
+// 1D grid of ntx * ntg * nch tiles (x tiles fastest, then TA groups, then
+// chunks along d). With CFL the kernel also reduces c_max of the state it
+// writes (the last sweep of a step), so the next step needs no extra pass.
+constexpr int MW = 4;   // wavefronts per marching workgroup
+
+struct MarchTile {
+    int i, tc, o0, o1;
+    bool active;
+};
+
+template <int D>
+__device__ __forceinline__ MarchTile march_tile(const Grid& g, int chunk)
+{
+    constexpr int TA = (D == 1) ? 2 : 1;
+    const int nx = g.n[0], nd = g.n[D], nt = g.n[TA];
+    const unsigned ntx = (nx + 63) / 64, ntg = (nt + MW - 1) / MW;
+    const unsigned lb = blockIdx.x;
+    const unsigned xt = lb % ntx, rest = lb / ntx;
+    const unsigned tg = rest % ntg, ch = rest / ntg;
+    MarchTile m;
+    m.i = xt * 64 + threadIdx.x;
+    m.tc = tg * MW + threadIdx.y;
+    m.o0 = ch * chunk;
+    m.o1 = min(m.o0 + chunk, nd);
+    m.active = m.i < nx && m.tc < nt && m.o0 < m.o1;
+    return m;
+}
+
+template <typename T, int D, bool CFL>
+__global__ void __launch_bounds__(64 * MW) fluid_march(const T* __restrict__ uin, T* __restrict__ uout,
+                                                       const T* __restrict__ bf, Grid g, T gamma,
+                                                       const Ctl* __restrict__ ctl, double dt_arg, int chunk,
+                                                       unsigned long long* __restrict__ parts)
 {
     constexpr int E = (D + 1) % 3, F = (D + 2) % 3;
     constexpr int TA = (D == 1) ? 2 : 1;
-    const int nx = g.n[0], nd = g.n[D], nt = g.n[TA];
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int tc = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= nx || tc >= nt) return;
-    const int o0 = blockIdx.z * chunk;
-    const int o1 = min(o0 + chunk, nd);
-    if (o0 >= o1) return;
-    const long long N = g.N;
-    const long long sd = (D == 1) ? (long long)nx : (long long)nx * g.n[1];
-    const long long st = (TA == 1) ? (long long)nx : (long long)nx * g.n[1];
-    const long long base = i + tc * st;
-    const long long xp = wrap_idx(i + 1, nx, g.bc) - i;
-    const long long tp = (long long)(wrap_idx(tc + 1, nt, g.bc) - tc) * st;
-    const long long offE = (E == 0) ? xp : tp;
-    const long long offF = (F == 0) ? xp : tp;
-    const T* rho = uin;
-    const T* mD = uin + (1 + D) * N;
-    const T* mE = uin + (1 + E) * N;
-    const T* mF = uin + (1 + F) * N;
-    const T* en = uin + 4 * N;
-    const T* BD = bf + D * N;
-    const T* BE = bf + E * N;
-    const T* BF = bf + F * N;
-    const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
-    const bool frozen = ctl->status != 0;
+    const MarchTile mt = march_tile<D>(g, chunk);
+    unsigned long long best = 0ull;
+    if (mt.active) {
+        const int nx = g.n[0], nd = g.n[D], nt = g.n[TA];
+        const int i = mt.i, tc = mt.tc, o0 = mt.o0, o1 = mt.o1;
+        const long long N = g.N;
+        const long long sd = (D == 1) ? (long long)nx : (long long)nx * g.n[1];
+        const long long st = (TA == 1) ? (long long)nx : (long long)nx * g.n[1];
+        const long long base = i + tc * st;
+        const long long xp = wrap_idx(i + 1, nx, g.bc) - i;
+        const long long tp = (long long)(wrap_idx(tc + 1, nt, g.bc) - tc) * st;
+        const long long offE = (E == 0) ? xp : tp;
+        const long long offF = (F == 0) ? xp : tp;
+        const T* rho = uin;
+        const T* mD = uin + (1 + D) * N;
+        const T* mE = uin + (1 + E) * N;
+        const T* mF = uin + (1 + F) * N;
+        const T* en = uin + 4 * N;
+        const T* BD = bf + D * N;
+        const T* BE = bf + E * N;
+        const T* BF = bf + F * N;
+        const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
+        const bool frozen = ctl->status != 0;
 
-    FluidPipe<T> P;
-    P.clear();
-    T bd_lo = BD[base + (long long)wrap_idx(o0 - GF, nd, g.bc) * sd];
-    for (int h = o0 - GF; h <= o1 + GF - 1; ++h) {
-        const long long c = base + (long long)wrap_idx(h, nd, g.bc) * sd;
-        const T bd_hi = BD[base + (long long)wrap_idx(h + 1, nd, g.bc) * sd];
-        T uh[5] = {rho[c], mD[c], mE[c], mF[c], en[c]};
-        T bh[3] = {T(0.5) * (bd_lo + bd_hi), T(0.5) * (BE[c] + BE[c + offE]), T(0.5) * (BF[c] + BF[c + offF])};
-        bd_lo = bd_hi;
-        const T keep[5] = {P.u3[0], P.u3[1], P.u3[2], P.u3[3], P.u3[4]};
-        T un[5];
-        P.push(uh, bh, gamma, dt, un);
-        const int o = h - GF;
-        if (o >= o0) {
-            const long long co = base + (long long)o * sd;
-            uout[co] = frozen ? keep[0] : un[0];
-            uout[(1 + D) * N + co] = frozen ? keep[1] : un[1];
-            uout[(1 + E) * N + co] = frozen ? keep[2] : un[2];
-            uout[(1 + F) * N + co] = frozen ? keep[3] : un[3];
-            uout[4 * N + co] = frozen ? keep[4] : un[4];
+        FluidPipe<T> P;
+        P.clear();
+        T bd_lo = BD[base + (long long)wrap_idx(o0 - GF, nd, g.bc) * sd];
+        for (int h = o0 - GF; h <= o1 + GF - 1; ++h) {
+            const long long c = base + (long long)wrap_idx(h, nd, g.bc) * sd;
+            const T bd_hi = BD[base + (long long)wrap_idx(h + 1, nd, g.bc) * sd];
+            T uh[5] = {rho[c], mD[c], mE[c], mF[c], en[c]};
+            T bh[3] = {T(0.5) * (bd_lo + bd_hi), T(0.5) * (BE[c] + BE[c + offE]),
+                       T(0.5) * (BF[c] + BF[c + offF])};
+            bd_lo = bd_hi;
+            const int o = h - GF;
+            const long long co = base + (long long)wrap_idx(o, nd, g.bc) * sd;
+            T keep[5];
+            if (o >= o0) {
+                keep[0] = rho[co];
+                keep[1] = mD[co];
+                keep[2] = mE[co];
+                keep[3] = mF[co];
+                keep[4] = en[co];
+            }
+            const T bo[3] = {P.b3[0], P.b3[1], P.b3[2]};   // centred field of the output cell
+            T un[5];
+            P.push(uh, bh, gamma, dt, keep, un);
+            if (o >= o0) {
+                if (frozen) {
+#pragma unroll
+                    for (int q = 0; q < 5; q++) un[q] = keep[q];
+                }
+                uout[co] = un[0];
+                uout[(1 + D) * N + co] = un[1];
+                uout[(1 + E) * N + co] = un[2];
+                uout[(1 + F) * N + co] = un[3];
+                uout[4 * N + co] = un[4];
+                if constexpr (CFL) {
+                    // back to x, y, z order: rotated slot of axis a is (a - D) mod 3
+                    const T cc = cfl_speed(un[0], un[1 + (3 - D) % 3], un[1 + (4 - D) % 3], un[1 + (5 - D) % 3],
+                                           un[4], bo[(3 - D) % 3], bo[(4 - D) % 3], bo[(5 - D) % 3], gamma);
+                    const unsigned long long bits = speed_bits(cc);
+                    best = bits > best ? bits : best;
+                }
+            }
         }
     }
+    if constexpr (CFL) block_max_to_part<64 * MW>(best, threadIdx.x + 64 * threadIdx.y, parts);
 }
 
 // B_{e->d}, B_{f->d} for d = y or z: marching kernel, same launch shape as
@@ -287,19 +438,16 @@ __global__ void __launch_bounds__(256) fluid_march(const T* __restrict__ uin, T*
 // through its own cells and through the +e / +f neighbours (their EMFs enter
 // the constraint update of B_d).
 template <typename T, int D>
-__global__ void __launch_bounds__(256) ct_march(const T* __restrict__ uf, const T* __restrict__ bin,
-                                                T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
-                                                double dt_arg, int chunk)
+__global__ void __launch_bounds__(64 * MW) ct_march(const T* __restrict__ uf, const T* __restrict__ bin,
+                                                    T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
+                                                    double dt_arg, int chunk)
 {
     constexpr int E = (D + 1) % 3, F = (D + 2) % 3;
     constexpr int TA = (D == 1) ? 2 : 1;
+    const MarchTile mt = march_tile<D>(g, chunk);
+    if (!mt.active) return;   // no barrier in this kernel
     const int nx = g.n[0], nd = g.n[D], nt = g.n[TA];
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int tc = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= nx || tc >= nt) return;
-    const int o0 = blockIdx.z * chunk;
-    const int o1 = min(o0 + chunk, nd);
-    if (o0 >= o1) return;
+    const int i = mt.i, tc = mt.tc, o0 = mt.o0, o1 = mt.o1;
     const long long N = g.N;
     const long long sd = (D == 1) ? (long long)nx : (long long)nx * g.n[1];
     const long long st = (TA == 1) ? (long long)nx : (long long)nx * g.n[1];
@@ -330,8 +478,6 @@ __global__ void __launch_bounds__(256) ct_march(const T* __restrict__ uf, const 
         const T rEp = rho[c + offEp], mEp = md[c + offEp];
         const T rFm = rho[c + offFm], mFm = md[c + offFm];
         const T rFp = rho[c + offFp], mFp = md[c + offFp];
-        // original transverse faces of the output cell h - 4
-        const T be = e0.B4, bfv = f0.B4;
         // face velocity along d on a transverse face: mass-weighted mean of the
         // two cells sharing it (Alg. 2 step 4)
         const T Ge0 = e0.push((mEm + m0) / (rEm + r0), BE[c], dt);
@@ -342,7 +488,7 @@ __global__ void __launch_bounds__(256) ct_march(const T* __restrict__ uf, const 
         if (o >= o0) {
             const long long co = base + (long long)o * sd;
             // e0.G5 etc. still hold the EMFs at edge o - 1/2 (updated below)
-            const T bd = BD[co];
+            const T bd = BD[co], be = BE[co], bfv = BF[co];
             if (frozen) {
                 bout[E * N + co] = be;
                 bout[F * N + co] = bfv;
@@ -366,10 +512,11 @@ __global__ void __launch_bounds__(256) ct_march(const T* __restrict__ uf, const 
 constexpr int XT = 256;   // threads per workgroup of the x kernels
 constexpr int XP = 2;     // passes (cells per thread)
 
-template <typename T>
+template <typename T, bool CFL>
 __global__ void __launch_bounds__(XT) fluid_x_lds(const T* __restrict__ uin, T* __restrict__ uout,
                                                   const T* __restrict__ bf, Grid g, T gamma,
-                                                  const Ctl* __restrict__ ctl, double dt_arg, int S, int R)
+                                                  const Ctl* __restrict__ ctl, double dt_arg, int S, int R,
+                                                  unsigned long long* __restrict__ parts)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sr = reinterpret_cast<T*>(smem_raw);
@@ -379,8 +526,10 @@ __global__ void __launch_bounds__(XT) fluid_x_lds(const T* __restrict__ uin, T* 
     const int nx = g.n[0], ny = g.n[1];
     const long long nrows = (long long)ny * g.n[2];
     const long long N = g.N;
-    const int o0 = blockIdx.y * S;
-    const long long row0 = (long long)blockIdx.x * R;
+    const unsigned nseg = (nx + S - 1) / S;
+    const unsigned lb = blockIdx.x;   // segments fastest, then row groups
+    const int o0 = (lb % nseg) * S;
+    const long long row0 = (long long)(lb / nseg) * R;
     const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
     const bool frozen = ctl->status != 0;
 
@@ -481,6 +630,7 @@ __global__ void __launch_bounds__(XT) fluid_x_lds(const T* __restrict__ uin, T* 
     }
     __syncthreads();
     // full update of the S owned cells per row (eq. Delta_u_full)
+    unsigned long long best = 0ull;
 #pragma unroll
     for (int p = 0; p < XP; p++) {
         const int m = m_[p];
@@ -488,14 +638,22 @@ __global__ void __launch_bounds__(XT) fluid_x_lds(const T* __restrict__ uin, T* 
         if (act[p] && m >= GF && m < Ext - GF && x < nx) {
             const int s = slot[p];
             const long long c = cidx[p];
+            T un[5];
 #pragma unroll
             for (int q = 0; q < 5; q++) {
                 const T fp = Rr[p][q] - sl[q * ncell + s + 1];
                 const T fm = sr[q * ncell + s - 1] - Ll[p][q];
-                uout[q * N + c] = frozen ? u[p][q] : u[p][q] - dt * (fp - fm);
+                un[q] = frozen ? u[p][q] : u[p][q] - dt * (fp - fm);
+                uout[q * N + c] = un[q];
+            }
+            if constexpr (CFL) {
+                const T cc = cfl_speed(un[0], un[1], un[2], un[3], un[4], b[p][0], b[p][1], b[p][2], gamma);
+                const unsigned long long bits = speed_bits(cc);
+                best = bits > best ? bits : best;
             }
         }
     }
+    if constexpr (CFL) block_max_to_part<XT>(best, threadIdx.x, parts);
 }
 
 // B_{y->x}, B_{z->x}: one workgroup stages R rows x (S + 8) cells in LDS and
@@ -515,8 +673,10 @@ __global__ void __launch_bounds__(XT) ct_x_lds(const T* __restrict__ uf, const T
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const long long nrows = (long long)ny * nz;
     const long long N = g.N;
-    const int o0 = blockIdx.y * S;
-    const long long row0 = (long long)blockIdx.x * R;
+    const unsigned nseg = (nx + S - 1) / S;
+    const unsigned lb = blockIdx.x;   // segments fastest, then row groups
+    const int o0 = (lb % nseg) * S;
+    const long long row0 = (long long)(lb / nseg) * R;
     const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
     const bool frozen = ctl->status != 0;
 
@@ -677,134 +837,41 @@ __global__ void __launch_bounds__(XT) ct_x_lds(const T* __restrict__ uf, const T
 }
 
 // ---------------------------------------------------------------------------
-// Reductions: running max of non-negative values as ordered bit patterns
-// (NaN compares above every finite value and +inf, so it propagates).
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const unsigned long long o = __shfl_xor(v, off, 64);
-        v = o > v ? o : v;
-    }
-    return v;
-}
-
-template <int BS>
-__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v)
-{
-    __shared__ unsigned long long part[BS / 64];
-    v = wave_max_u64(v);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) part[w] = v;
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        v = threadIdx.x < BS / 64 ? part[threadIdx.x] : 0ull;
-        v = wave_max_u64(v);
-    }
-    return v;
-}
-
-__device__ __forceinline__ unsigned long long as_bits(double x)
-{
-    // non-negative or NaN inputs only; negative NaNs also sort above +inf
-    return (unsigned long long)__double_as_longlong(x);
-}
-
 constexpr int RB = 256;   // threads per block of the reductions
 
-// Per-cell CFL speed of eq. equat_CFL, global max, and (last block) the
-// time-step rule: dt = cfl / c_max, clipped so that t lands on t_stop.
-template <typename T, bool SETDT>
+// Per-cell CFL speed of eq. equat_CFL; per-block maxima into parts.
+template <typename T>
 __global__ void __launch_bounds__(RB) cfl_kernel(const T* __restrict__ u, const T* __restrict__ b, Grid g,
-                                                 T gamma, double cfl, Ctl* ctl)
+                                                 T gamma, unsigned long long* __restrict__ parts)
 {
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const long long N = g.N;
     unsigned long long best = 0ull;
-    // one x-row (j, k) per loop trip of a block, lanes along x: no integer division
+    // one x-row (j, k) per loop trip of a block, lanes along x
     const long long nrows = (long long)ny * nz;
     for (long long row = blockIdx.x; row < nrows; row += gridDim.x) {
-      const int j = (int)(row % ny), k = (int)(row / ny);
-      const long long rb = row * nx;
-      const long long yoff = (long long)(wrap_idx(j + 1, ny, g.bc) - j) * nx;
-      const long long zoff = (long long)(wrap_idx(k + 1, nz, g.bc) - k) * nx * ny;
-      for (int i = threadIdx.x; i < nx; i += RB) {
-        const long long c = rb + i;
-        const long long cxp = rb + wrap_idx(i + 1, nx, g.bc);
-        const long long cyp = c + yoff;
-        const long long czp = c + zoff;
-        const T rho = u[c];
-        const T bx = T(0.5) * (b[c] + b[cxp]);
-        const T by = T(0.5) * (b[N + c] + b[N + cyp]);
-        const T bz = T(0.5) * (b[2 * N + c] + b[2 * N + czp]);
-        const T bb = bx * bx + by * by + bz * bz;
-        T cc;
-        if constexpr (kExact<T>) {
-            const T vx = u[N + c] / rho, vy = u[2 * N + c] / rho, vz = u[3 * N + c] / rho;
-            const T vv = vx * vx + vy * vy + vz * vz;
-            const T p = (gamma - T(1)) * (u[4 * N + c] - T(0.5) * rho * vv - T(0.5) * bb);
-            const T vm = fmax(fabs(vx), fmax(fabs(vy), fabs(vz)));
-            cc = vm + sqrt(fabs(gamma * p + bb) / rho);
-        } else {
-            const T rinv = T(1) / rho;
-            const T vx = u[N + c] * rinv, vy = u[2 * N + c] * rinv, vz = u[3 * N + c] * rinv;
-            const T ke = T(0.5) * (u[N + c] * vx + u[2 * N + c] * vy + u[3 * N + c] * vz);
-            const T p = (gamma - T(1)) * (u[4 * N + c] - ke - T(0.5) * bb);
-            const T vm = fmax(fabs(vx), fmax(fabs(vy), fabs(vz)));
-            cc = vm + sqrt(fabs(gamma * p + bb) * rinv);
-        }
-        if (cc != cc) cc = (T)__builtin_nan("");   // canonical positive NaN
-        const unsigned long long bits = as_bits((double)cc);
-        best = bits > best ? bits : best;
-      }
-    }
-    best = block_max_u64<RB>(best);
-    __shared__ bool last;
-    if (threadIdx.x == 0) {
-        atomicMax(&ctl->max_bits, best);
-        __threadfence();
-        last = atomicAdd(&ctl->blocks_done, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
-        const unsigned long long mb = atomicMax(&ctl->max_bits, 0ull);
-        const double cmax = __longlong_as_double((long long)mb);
-        ctl->cmax = cmax;
-        ctl->max_bits = 0ull;
-        ctl->blocks_done = 0u;
-        if (SETDT) {
-            double dt = 0.0, t = ctl->t;
-            if (ctl->status == 0) {
-                if (!(cmax > 0.0) || cmax > 1.7976931348623157e308) {
-                    ctl->status = -4;
-                } else {
-                    double h = cfl / cmax;
-                    double tn = t + 2.0 * h;
-                    const double ts = ctl->t_stop;
-                    if (ts >= 0.0) {
-                        const double rem = ts - t;
-                        if (rem <= 0.0) {
-                            h = 0.0;
-                            tn = t;
-                        } else if (2.0 * h >= rem) {
-                            h = rem / 2.0;
-                            tn = ts;
-                        }
-                    }
-                    dt = h;
-                    t = tn;
-                }
-            }
-            ctl->dt = dt;
-            ctl->t = t;
+        const int j = (int)(row % ny), k = (int)(row / ny);
+        const long long rb = row * nx;
+        const long long yoff = (long long)(wrap_idx(j + 1, ny, g.bc) - j) * nx;
+        const long long zoff = (long long)(wrap_idx(k + 1, nz, g.bc) - k) * nx * ny;
+        for (int i = threadIdx.x; i < nx; i += RB) {
+            const long long c = rb + i;
+            const long long cxp = rb + wrap_idx(i + 1, nx, g.bc);
+            const T bx = T(0.5) * (b[c] + b[cxp]);
+            const T by = T(0.5) * (b[N + c] + b[N + c + yoff]);
+            const T bz = T(0.5) * (b[2 * N + c] + b[2 * N + c + zoff]);
+            const T cc = cfl_speed(u[c], u[N + c], u[2 * N + c], u[3 * N + c], u[4 * N + c], bx, by, bz, gamma);
+            const unsigned long long bits = speed_bits(cc);
+            best = bits > best ? bits : best;
         }
     }
+    block_max_to_part<RB>(best, threadIdx.x, parts);
 }
 
 // max over cells of |div B| (cells whose upper faces are stored)
 template <typename T>
-__global__ void __launch_bounds__(RB) divb_kernel(const T* __restrict__ b, Grid g, Ctl* ctl)
+__global__ void __launch_bounds__(RB) divb_kernel(const T* __restrict__ b, Grid g,
+                                                  unsigned long long* __restrict__ parts)
 {
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const long long N = g.N;
@@ -825,27 +892,11 @@ __global__ void __launch_bounds__(RB) divb_kernel(const T* __restrict__ b, Grid 
         double d = (double)(b[cxp] - b[c]);
         d += (double)(b[N + cyp] - b[N + c]);
         d += (double)(b[2 * N + czp] - b[2 * N + c]);
-        d = fabs(d);
-        if (d != d) d = __builtin_nan("");
-        const unsigned long long bits = as_bits(d);
+        const unsigned long long bits = speed_bits(fabs(d));
         best = bits > best ? bits : best;
       }
     }
-    best = block_max_u64<RB>(best);
-    __shared__ bool last;
-    if (threadIdx.x == 0) {
-        atomicMax(&ctl->div_bits, best);
-        __threadfence();
-        last = atomicAdd(&ctl->div_blocks_done, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
-        const unsigned long long mb = atomicMax(&ctl->div_bits, 0ull);
-        ctl->cmax = __longlong_as_double((long long)mb);   // result slot read by the host
-        ctl->div_bits = 0ull;
-        ctl->div_blocks_done = 0u;
-    }
+    block_max_to_part<RB>(best, threadIdx.x, parts);
 }
 
 int reduce_blocks(const Grid& g)
@@ -873,37 +924,12 @@ int march_chunk(const Grid& g, int d, int ghost)
     return chunk;
 }
 
-constexpr int MW = 4;   // wavefronts per marching workgroup
-
 }  // namespace
 
-template <typename T>
-hipError_t launch_cfl(const T* u, const T* b, Grid g, double gamma, double cfl, Ctl* ctl, hipStream_t s)
-{
-    hipLaunchKernelGGL((cfl_kernel<T, true>), dim3(reduce_blocks(g)), dim3(RB), 0, s, u, b, g, (T)gamma, cfl, ctl);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_cmax_only(const T* u, const T* b, Grid g, double gamma, Ctl* ctl, hipStream_t s)
-{
-    hipLaunchKernelGGL((cfl_kernel<T, false>), dim3(reduce_blocks(g)), dim3(RB), 0, s, u, b, g, (T)gamma, 0.0,
-                       ctl);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_divb(const T* b, Grid g, Ctl* ctl, hipStream_t s)
-{
-    hipLaunchKernelGGL((divb_kernel<T>), dim3(reduce_blocks(g)), dim3(RB), 0, s, b, g, ctl);
-    return hipGetLastError();
-}
-
-template <typename T>
+// one segment per row if it fits XT * XP cells, several rows per workgroup
+// when rows are short
 static void x_tile(const Grid& g, int ghost, int& S, int& R)
 {
-    // one segment per row if it fits XT * XP cells, several rows per workgroup
-    // when rows are short
     const int cap = XT * XP;
     const int nx = g.n[0];
     int nseg = 1;
@@ -915,26 +941,71 @@ static void x_tile(const Grid& g, int ghost, int& S, int& R)
     if (R > nrows) R = (int)nrows;
 }
 
-template <typename T>
-hipError_t launch_fluid(int axis, const T* u_in, T* u_out, const T* b, Grid g, double gamma, const Ctl* ctl,
-                        double dt, hipStream_t s)
+static unsigned x_blocks(const Grid& g, int S, int R)
 {
+    const long long nrows = (long long)g.n[1] * g.n[2];
+    return (unsigned)(((nrows + R - 1) / R) * ((g.n[0] + S - 1) / S));
+}
+
+static unsigned march_blocks(const Grid& g, int axis, int chunk)
+{
+    const int ta = (axis == 1) ? 2 : 1;
+    return (unsigned)(((g.n[0] + 63) / 64) * ((g.n[ta] + MW - 1) / MW) * ((g.n[axis] + chunk - 1) / chunk));
+}
+
+template <typename T>
+hipError_t launch_cfl(const T* u, const T* b, Grid g, double gamma, unsigned long long* parts, int* nparts,
+                      hipStream_t s)
+{
+    const int nb = reduce_blocks(g);
+    hipLaunchKernelGGL((cfl_kernel<T>), dim3(nb), dim3(RB), 0, s, u, b, g, (T)gamma, parts);
+    *nparts = nb;
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_divb(const T* b, Grid g, unsigned long long* parts, int* nparts, hipStream_t s)
+{
+    const int nb = reduce_blocks(g);
+    hipLaunchKernelGGL((divb_kernel<T>), dim3(nb), dim3(RB), 0, s, b, g, parts);
+    *nparts = nb;
+    return hipGetLastError();
+}
+
+template <typename T, bool CFL>
+static void fluid_launch(int axis, const T* u_in, T* u_out, const T* b, Grid g, double gamma, const Ctl* ctl,
+                         double dt, unsigned long long* parts, int* nparts, hipStream_t s)
+{
+    unsigned nb;
     if (axis == 0) {
         int S, R;
-        x_tile<T>(g, GF, S, R);
-        const long long nrows = (long long)g.n[1] * g.n[2];
-        dim3 grid((unsigned)((nrows + R - 1) / R), (g.n[0] + S - 1) / S);
+        x_tile(g, GF, S, R);
+        nb = x_blocks(g, S, R);
         const size_t lds = sizeof(T) * 10 * (size_t)R * (S + 2 * GF);
-        hipLaunchKernelGGL((fluid_x_lds<T>), grid, dim3(XT), lds, s, u_in, u_out, b, g, (T)gamma, ctl, dt, S, R);
+        hipLaunchKernelGGL((fluid_x_lds<T, CFL>), dim3(nb), dim3(XT), lds, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
+                           S, R, parts);
     } else {
         const int chunk = march_chunk(g, axis, GF);
-        const int ta = (axis == 1) ? 2 : 1;
-        dim3 grid((g.n[0] + 63) / 64, (g.n[ta] + MW - 1) / MW, (g.n[axis] + chunk - 1) / chunk);
+        nb = march_blocks(g, axis, chunk);
+        const dim3 block(64, MW);
         if (axis == 1)
-            hipLaunchKernelGGL((fluid_march<T, 1>), grid, dim3(64, MW), 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt, chunk);
+            hipLaunchKernelGGL((fluid_march<T, 1, CFL>), dim3(nb), block, 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
+                               chunk, parts);
         else
-            hipLaunchKernelGGL((fluid_march<T, 2>), grid, dim3(64, MW), 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt, chunk);
+            hipLaunchKernelGGL((fluid_march<T, 2, CFL>), dim3(nb), block, 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
+                               chunk, parts);
     }
+    if (nparts) *nparts = (int)nb;
+}
+
+template <typename T>
+hipError_t launch_fluid(int axis, const T* u_in, T* u_out, const T* b, Grid g, double gamma, const Ctl* ctl,
+                        double dt, unsigned long long* parts, int* nparts, hipStream_t s)
+{
+    if (parts)
+        fluid_launch<T, true>(axis, u_in, u_out, b, g, gamma, ctl, dt, parts, nparts, s);
+    else
+        fluid_launch<T, false>(axis, u_in, u_out, b, g, gamma, ctl, dt, nullptr, nullptr, s);
     return hipGetLastError();
 }
 
@@ -944,22 +1015,19 @@ hipError_t launch_ct(int axis, const T* u, const T* b_in, T* b_out, Grid g, cons
 {
     if (axis == 0) {
         int S, R;
-        x_tile<T>(g, GB, S, R);
-        const long long nrows = (long long)g.n[1] * g.n[2];
-        dim3 grid((unsigned)((nrows + R - 1) / R), (g.n[0] + S - 1) / S);
+        x_tile(g, GB, S, R);
         const size_t lds = sizeof(T) * 12 * (size_t)R * (S + 2 * GB);
-        hipLaunchKernelGGL((ct_x_lds<T>), grid, dim3(XT), lds, s, u, b_in, b_out, g, ctl, dt, S, R);
+        hipLaunchKernelGGL((ct_x_lds<T>), dim3(x_blocks(g, S, R)), dim3(XT), lds, s, u, b_in, b_out, g, ctl, dt, S,
+                           R);
     } else {
         const int chunk = march_chunk(g, axis, GB);
-        const int ta = (axis == 1) ? 2 : 1;
-        dim3 grid((g.n[0] + 63) / 64, (g.n[ta] + MW - 1) / MW, (g.n[axis] + chunk - 1) / chunk);
+        const dim3 grid(march_blocks(g, axis, chunk)), block(64, MW);
         if (axis == 1)
-            hipLaunchKernelGGL((ct_march<T, 1>), grid, dim3(64, MW), 0, s, u, b_in, b_out, g, ctl, dt, chunk);
+            hipLaunchKernelGGL((ct_march<T, 1>), grid, block, 0, s, u, b_in, b_out, g, ctl, dt, chunk);
         else
-            hipLaunchKernelGGL((ct_march<T, 2>), grid, dim3(64, MW), 0, s, u, b_in, b_out, g, ctl, dt, chunk);
+            hipLaunchKernelGGL((ct_march<T, 2>), grid, block, 0, s, u, b_in, b_out, g, ctl, dt, chunk);
     }
     return hipGetLastError();
 }
-
 
 }  // namespace mhd

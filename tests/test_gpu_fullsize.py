@@ -79,17 +79,20 @@ def test_blast_256_one_step_sampled(B, blast_ref, dtype):
     worst = 0.0
     for (want, idx), c in zip(blocks, CENTRES):
         got = gpu_block(st, idx)
-        for f in range(8):
-            if dtype == "f64":
+        if dtype == "f64":
+            for f in range(8):
                 assert H.rel_linf(got[f], want[f]) <= 1e-10, (c, f)
-            else:
-                worst = max(worst, H.rel_l1(got[f], want[f]))
+        else:
+            # whole state of the block, so that a field that is nearly zero
+            # there (a momentum component on a symmetry plane) is measured
+            # against the size of the state, not against its own tiny values
+            worst = max(worst, H.rel_l1(got, want))
     if dtype == "f32":
-        # a shock problem: the FP32 error is reported, and only gated against
+        # a shock problem: the FP32 error is reported and only gated against
         # gross mistakes (single-precision rounding can flip the upwind choice
         # at the exact ties this symmetric problem produces)
-        note("blast 256^3 fp32 vs fp64 oracle, one step: worst rel L1 per field %.2e" % worst)
-        assert worst <= 1e-3
+        note("blast 256^3 fp32 vs fp64 oracle, one step: worst rel L1 of a block %.2e" % worst)
+        assert worst <= 1e-4
 
 
 def test_blast_256_invariants(B):
