@@ -16,6 +16,7 @@ sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -68,7 +69,34 @@ def run_gpu(B, P, n, dtype, warmup, steps, stream):
     return (t1 - t0), kern, divb, t_sim, s_done
 
 
-def roofline(kern, ncell, esize):
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "blast256_traffic.txt")
+KERNEL_SOURCE = os.path.join(HERE, "paper_0908_4362_amd", "csrc", "mhd_kernels_impl.h")
+
+
+def measured_traffic(prec, kind, n):
+    """HBM bytes per launch of one kernel kind from the committed counter summary, or None when the
+    summary is for another workload or the kernel source has changed since the counters were taken."""
+    if n != 256 or not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(KERNEL_SOURCE, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+    table, src = {}, None
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            f = line.split()
+            if not f or f[0].startswith("#"):
+                continue
+            if f[0] == "source_sha256":
+                src = f[1]
+            elif len(f) == 4:
+                table[(f[0], f[1])] = int(f[2]) + int(f[3])
+    if src != sha:
+        return None
+    return table.get((prec, kind))
+
+
+def roofline(kern, ncell, esize, n):
     total = {k: v[0] for k, v in kern.items() if v[1] > 0}
     dom = max(total, key=total.get)
     ms, cnt = kern[dom]
@@ -82,7 +110,7 @@ def roofline(kern, ncell, esize):
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": measured_traffic("f64" if esize == 8 else "f32", dom, n),
         "avg_launch_ms": round(ms / cnt, 5),
         "bytes_per_launch": bytes_per_launch,
     }
@@ -159,7 +187,7 @@ def main():
     print("bench: %d^3 blast, fp64, %d warm-up + %d timed steps" % (n, args.warmup, args.steps), file=sys.stderr,
           flush=True)
     sec64, kern64, divb64, tsim, sdone = run_gpu(B, P, n, B.MHD_F64, args.warmup, args.steps, stream)
-    dom, roof = roofline(kern64, ncell, 8)
+    dom, roof = roofline(kern64, ncell, 8, n)
     out = {
         "metric": "cell-updates/s per full step",
         "value": round(ncell * args.steps / sec64, 1),
@@ -183,7 +211,7 @@ def main():
     if not args.no_fp32:
         print("bench: %d^3 blast, fp32" % n, file=sys.stderr, flush=True)
         sec32, kern32, divb32, _, _ = run_gpu(B, P, n, B.MHD_F32, args.warmup, args.steps, stream)
-        _, roof32 = roofline(kern32, ncell, 4)
+        _, roof32 = roofline(kern32, ncell, 4, n)
         out["fp32"] = {
             "value": round(ncell * args.steps / sec32, 1),
             "ms_per_step": round(sec32 * 1e3 / args.steps, 4),

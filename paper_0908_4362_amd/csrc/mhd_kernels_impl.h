@@ -113,14 +113,14 @@ __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v
     return v;
 }
 
-// Grid-wide max, first level: every block stores its maximum in
-// parts[blockIdx.x] (plain stores, no atomics); a one-block finisher reduces
+// Grid-wide max, first level: every block stores its maximum in its own slot
+// of a parts array (plain stores, no atomics); a one-block finisher reduces
 // the parts.
 template <int BS>
-__device__ __forceinline__ void block_max_to_part(unsigned long long v, int tid, unsigned long long* parts)
+__device__ __forceinline__ void block_max_to_part(unsigned long long v, int tid, unsigned long long* slot)
 {
     v = block_max_u64<BS>(v, tid);
-    if (tid == 0) parts[blockIdx.x] = v;
+    if (tid == 0) *slot = v;
 }
 
 // Time-step rule (Sec. 4.2, eq. equat_CFL): dt = cfl / c_max, clipped so that
@@ -207,7 +207,7 @@ template <typename T>
 struct FluidPipe {
     T r1[5];          // r at h-1
     T f1[5];          // first-order flux at (h-1) - 1/2
-    T u1[5];          // conserved state at h-1
+    T u1[5], u2[5], u3[5];  // conserved state at h-1, h-2, h-3
     T b1[3], b2[3], b3[3];  // centred field at h-1, h-2, h-3
     T rp2[5], rp3[5], lp2[5], lp3[5];  // movers of u^{t+dt/2} at h-2, h-3
     T R3[5];          // limited right mover at h-3
@@ -217,7 +217,7 @@ struct FluidPipe {
     {
 #pragma unroll
         for (int q = 0; q < 5; q++) {
-            r1[q] = f1[q] = u1[q] = T(0);
+            r1[q] = f1[q] = u1[q] = u2[q] = u3[q] = T(0);
             rp2[q] = rp3[q] = lp2[q] = lp3[q] = R3[q] = f2[q] = T(0);
         }
         b1[0] = b1[1] = b1[2] = T(0);
@@ -225,9 +225,7 @@ struct FluidPipe {
         b3[0] = b3[1] = b3[2] = T(0);
     }
 
-    // u3 is the state of the output cell h - 3 (re-read by the caller rather
-    // than carried, to keep the register window small).
-    __device__ __forceinline__ void push(const T* uh, const T* bh, T gamma, T dt, const T* u3, T* unew)
+    __device__ __forceinline__ void push(const T* uh, const T* bh, T gamma, T dt, T* unew)
     {
         T rh[5], lh[5];
         movers(uh, bh, gamma, rh, lh);
@@ -264,6 +262,8 @@ struct FluidPipe {
             lp2[q] = lp1[q];
             f1[q] = fh[q];
             r1[q] = rh[q];
+            u3[q] = u2[q];
+            u2[q] = u1[q];
             u1[q] = uh[q];
         }
 #pragma unroll
@@ -282,7 +282,7 @@ template <typename T>
 struct EmfPipe {
     T vh1, vh2;       // raw face velocity at h-1, h-2
     T v2;             // smoothed velocity at h-2
-    T B1, B2;         // face field at h-1, h-2
+    T B1, B2, B3, B4; // face field at h-1 .. h-4
     T g3;             // first-order EMF at edge (h-3) + 1/2
     T qh3, qh4;       // v B^{t+dt/2} at h-3, h-4
     T s4;             // limited slope at h-4
@@ -291,7 +291,7 @@ struct EmfPipe {
 
     __device__ __forceinline__ void clear()
     {
-        vh1 = vh2 = v2 = B1 = B2 = g3 = qh3 = qh4 = s4 = e3 = e4 = G5 = T(0);
+        vh1 = vh2 = v2 = B1 = B2 = B3 = B4 = g3 = qh3 = qh4 = s4 = e3 = e4 = G5 = T(0);
     }
 
     __device__ __forceinline__ T push(T vhat, T Bh, T dt)
@@ -315,6 +315,8 @@ struct EmfPipe {
         qh4 = qh3;
         qh3 = qh2;
         g3 = g2;
+        B4 = B3;
+        B3 = B2;
         B2 = B1;
         B1 = Bh;
         v2 = v1;
@@ -324,6 +326,7 @@ struct EmfPipe {
     }
 };
 
+// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // fluid_d for d = y (D = 1) or z (D = 2): marching kernel.
 // Block (64, MW): lanes along x, MW wavefronts along the remaining axis TA;
@@ -338,12 +341,11 @@ struct MarchTile {
 };
 
 template <int D>
-__device__ __forceinline__ MarchTile march_tile(const Grid& g, int chunk)
+__device__ __forceinline__ MarchTile march_tile(const Grid& g, int chunk, unsigned lb)
 {
     constexpr int TA = (D == 1) ? 2 : 1;
     const int nx = g.n[0], nd = g.n[D], nt = g.n[TA];
     const unsigned ntx = (nx + 63) / 64, ntg = (nt + MW - 1) / MW;
-    const unsigned lb = blockIdx.x;
     const unsigned xt = lb % ntx, rest = lb / ntx;
     const unsigned tg = rest % ntg, ch = rest / ntg;
     MarchTile m;
@@ -355,171 +357,257 @@ __device__ __forceinline__ MarchTile march_tile(const Grid& g, int chunk)
     return m;
 }
 
+// Marching kernels: each thread walks its pencil cell by cell. The global
+// loads of cell h + 1 are issued before the arithmetic of cell h, so their
+// latency overlaps it (the compiler does not pipeline the loop by itself).
+// Neighbour values across x come from the adjacent lanes' cache lines, those
+// across the other transverse axis TA from the neighbouring pencil, read
+// directly (an LDS exchange between the wavefronts of a workgroup costs a
+// barrier per cell and measured slower).
+template <typename T>
+struct FluidLoad {
+    T u[5];
+    T bd1;        // B_d on the upper d-face
+    T bt0, bt1;   // transverse face field (axis TA) on the lower / upper face
+    T bx0, bx1;   // x face field on the lower / upper face
+};
+
+template <typename T, int D, bool CFL>
+__device__ __forceinline__ void fluid_march_body(const T* __restrict__ uin, T* __restrict__ uout,
+                                                 const T* __restrict__ bf, const Grid& g, T gamma,
+                                                 const Ctl* __restrict__ ctl, double dt_arg, int chunk, unsigned lb,
+                                                 unsigned long long* __restrict__ part)
+{
+    constexpr int E = (D + 1) % 3, F = (D + 2) % 3;
+    constexpr int TA = (D == 1) ? 2 : 1;
+    // the transverse axis TA is E for a sweep along y and F for a sweep along z
+    constexpr bool T_IS_E = (E == TA);
+    const MarchTile mt = march_tile<D>(g, chunk, lb);
+    const int nx = g.n[0], nd = g.n[D], nt = g.n[TA];
+    const int o0 = mt.o0, o1 = mt.o1;
+    const int i = wrap_idx(mt.i, nx, g.bc), tc = wrap_idx(mt.tc, nt, g.bc);
+    const bool active = mt.active;
+    const long long N = g.N;
+    const long long sd = (D == 1) ? (long long)nx : (long long)nx * g.n[1];
+    const long long st = (TA == 1) ? (long long)nx : (long long)nx * g.n[1];
+    const long long base = i + tc * st;
+    const long long offX = wrap_idx(i + 1, nx, g.bc) - i;
+    const long long offT = (long long)(wrap_idx(mt.tc + 1, nt, g.bc) - tc) * st;
+    const T* rho = uin;
+    const T* mD = uin + (1 + D) * N;
+    const T* mE = uin + (1 + E) * N;
+    const T* mF = uin + (1 + F) * N;
+    const T* en = uin + 4 * N;
+    const T* BD = bf + D * N;
+    const T* BT = bf + (T_IS_E ? E : F) * N;
+    const T* BX = bf + (T_IS_E ? F : E) * N;
+    const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
+    const bool frozen = ctl->status != 0;
+    unsigned long long best = 0ull;
+
+    auto load = [&](int h, FluidLoad<T>& L) {
+        const long long c = base + (long long)wrap_idx(h, nd, g.bc) * sd;
+        L.u[0] = rho[c];
+        L.u[1] = mD[c];
+        L.u[2] = mE[c];
+        L.u[3] = mF[c];
+        L.u[4] = en[c];
+        L.bd1 = BD[base + (long long)wrap_idx(h + 1, nd, g.bc) * sd];
+        L.bt0 = BT[c];
+        L.bt1 = BT[c + offT];
+        L.bx0 = BX[c];
+        L.bx1 = BX[c + offX];
+    };
+
+    FluidPipe<T> P;
+    P.clear();
+    T bd_lo = BD[base + (long long)wrap_idx(o0 - GF, nd, g.bc) * sd];
+    FluidLoad<T> cur;
+    load(o0 - GF, cur);
+    for (int h = o0 - GF; h <= o1 + GF - 1; ++h) {
+        FluidLoad<T> nxt;
+        load(h + 1, nxt);   // one cell past the end is a valid (mapped) cell
+        const T bT = T(0.5) * (cur.bt0 + cur.bt1), bX = T(0.5) * (cur.bx0 + cur.bx1);
+        T bh[3] = {T(0.5) * (bd_lo + cur.bd1), T_IS_E ? bT : bX, T_IS_E ? bX : bT};
+        bd_lo = cur.bd1;
+        const T keep[5] = {P.u3[0], P.u3[1], P.u3[2], P.u3[3], P.u3[4]};
+        const T bo[3] = {P.b3[0], P.b3[1], P.b3[2]};   // centred field of the output cell
+        T un[5];
+        P.push(cur.u, bh, gamma, dt, un);
+        const int o = h - GF;
+        if (active && o >= o0) {
+            if (frozen) {
+#pragma unroll
+                for (int q = 0; q < 5; q++) un[q] = keep[q];
+            }
+            const long long co = base + (long long)o * sd;
+            uout[co] = un[0];
+            uout[(1 + D) * N + co] = un[1];
+            uout[(1 + E) * N + co] = un[2];
+            uout[(1 + F) * N + co] = un[3];
+            uout[4 * N + co] = un[4];
+            if constexpr (CFL) {
+                // back to x, y, z order: rotated slot of axis a is (a - D) mod 3
+                const T cc = cfl_speed(un[0], un[1 + (3 - D) % 3], un[1 + (4 - D) % 3], un[1 + (5 - D) % 3],
+                                       un[4], bo[(3 - D) % 3], bo[(4 - D) % 3], bo[(5 - D) % 3], gamma);
+                const unsigned long long bits = speed_bits(cc);
+                best = bits > best ? bits : best;
+            }
+        }
+        cur = nxt;
+    }
+    if constexpr (CFL) block_max_to_part<64 * MW>(best, threadIdx.x + 64 * threadIdx.y, part);
+}
+
 template <typename T, int D, bool CFL>
 __global__ void __launch_bounds__(64 * MW) fluid_march(const T* __restrict__ uin, T* __restrict__ uout,
                                                        const T* __restrict__ bf, Grid g, T gamma,
                                                        const Ctl* __restrict__ ctl, double dt_arg, int chunk,
                                                        unsigned long long* __restrict__ parts)
 {
-    constexpr int E = (D + 1) % 3, F = (D + 2) % 3;
-    constexpr int TA = (D == 1) ? 2 : 1;
-    const MarchTile mt = march_tile<D>(g, chunk);
-    unsigned long long best = 0ull;
-    if (mt.active) {
-        const int nx = g.n[0], nd = g.n[D], nt = g.n[TA];
-        const int i = mt.i, tc = mt.tc, o0 = mt.o0, o1 = mt.o1;
-        const long long N = g.N;
-        const long long sd = (D == 1) ? (long long)nx : (long long)nx * g.n[1];
-        const long long st = (TA == 1) ? (long long)nx : (long long)nx * g.n[1];
-        const long long base = i + tc * st;
-        const long long xp = wrap_idx(i + 1, nx, g.bc) - i;
-        const long long tp = (long long)(wrap_idx(tc + 1, nt, g.bc) - tc) * st;
-        const long long offE = (E == 0) ? xp : tp;
-        const long long offF = (F == 0) ? xp : tp;
-        const T* rho = uin;
-        const T* mD = uin + (1 + D) * N;
-        const T* mE = uin + (1 + E) * N;
-        const T* mF = uin + (1 + F) * N;
-        const T* en = uin + 4 * N;
-        const T* BD = bf + D * N;
-        const T* BE = bf + E * N;
-        const T* BF = bf + F * N;
-        const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
-        const bool frozen = ctl->status != 0;
-
-        FluidPipe<T> P;
-        P.clear();
-        T bd_lo = BD[base + (long long)wrap_idx(o0 - GF, nd, g.bc) * sd];
-        for (int h = o0 - GF; h <= o1 + GF - 1; ++h) {
-            const long long c = base + (long long)wrap_idx(h, nd, g.bc) * sd;
-            const T bd_hi = BD[base + (long long)wrap_idx(h + 1, nd, g.bc) * sd];
-            T uh[5] = {rho[c], mD[c], mE[c], mF[c], en[c]};
-            T bh[3] = {T(0.5) * (bd_lo + bd_hi), T(0.5) * (BE[c] + BE[c + offE]),
-                       T(0.5) * (BF[c] + BF[c + offF])};
-            bd_lo = bd_hi;
-            const int o = h - GF;
-            const long long co = base + (long long)wrap_idx(o, nd, g.bc) * sd;
-            T keep[5];
-            if (o >= o0) {
-                keep[0] = rho[co];
-                keep[1] = mD[co];
-                keep[2] = mE[co];
-                keep[3] = mF[co];
-                keep[4] = en[co];
-            }
-            const T bo[3] = {P.b3[0], P.b3[1], P.b3[2]};   // centred field of the output cell
-            T un[5];
-            P.push(uh, bh, gamma, dt, keep, un);
-            if (o >= o0) {
-                if (frozen) {
-#pragma unroll
-                    for (int q = 0; q < 5; q++) un[q] = keep[q];
-                }
-                uout[co] = un[0];
-                uout[(1 + D) * N + co] = un[1];
-                uout[(1 + E) * N + co] = un[2];
-                uout[(1 + F) * N + co] = un[3];
-                uout[4 * N + co] = un[4];
-                if constexpr (CFL) {
-                    // back to x, y, z order: rotated slot of axis a is (a - D) mod 3
-                    const T cc = cfl_speed(un[0], un[1 + (3 - D) % 3], un[1 + (4 - D) % 3], un[1 + (5 - D) % 3],
-                                           un[4], bo[(3 - D) % 3], bo[(4 - D) % 3], bo[(5 - D) % 3], gamma);
-                    const unsigned long long bits = speed_bits(cc);
-                    best = bits > best ? bits : best;
-                }
-            }
-        }
-    }
-    if constexpr (CFL) block_max_to_part<64 * MW>(best, threadIdx.x + 64 * threadIdx.y, parts);
+    const unsigned lb = blockIdx.x;
+    fluid_march_body<T, D, CFL>(uin, uout, bf, g, gamma, ctl, dt_arg, chunk, lb, parts + blockIdx.x);
 }
 
 // B_{e->d}, B_{f->d} for d = y or z: marching kernel, same launch shape as
-// fluid_march. Each thread runs four EMF pipelines: the e- and f-face pencils
-// through its own cells and through the +e / +f neighbours (their EMFs enter
+// fluid_march. Each thread runs four EMF pipelines: the TA- and x-face pencils
+// through its own cells and through the +TA / +x neighbours (their EMFs enter
 // the constraint update of B_d).
+template <typename T>
+struct CtLoad {
+    T r0, m0, bt;            // own cell: rho, m_d, TA face field
+    T rTm, mTm, rTp, mTp, bt1;   // TA -1 / +1 neighbours
+    T rXm, mXm, rXp, mXp, bx0, bx1;
+};
+
 template <typename T, int D>
-__global__ void __launch_bounds__(64 * MW) ct_march(const T* __restrict__ uf, const T* __restrict__ bin,
-                                                    T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
-                                                    double dt_arg, int chunk)
+__device__ __forceinline__ void ct_march_body(const T* __restrict__ uf, const T* __restrict__ bin,
+                                              T* __restrict__ bout, const Grid& g, const Ctl* __restrict__ ctl,
+                                              double dt_arg, int chunk, unsigned lb)
 {
     constexpr int E = (D + 1) % 3, F = (D + 2) % 3;
     constexpr int TA = (D == 1) ? 2 : 1;
-    const MarchTile mt = march_tile<D>(g, chunk);
-    if (!mt.active) return;   // no barrier in this kernel
+    constexpr bool T_IS_E = (E == TA);
+    const MarchTile mt = march_tile<D>(g, chunk, lb);
     const int nx = g.n[0], nd = g.n[D], nt = g.n[TA];
-    const int i = mt.i, tc = mt.tc, o0 = mt.o0, o1 = mt.o1;
+    const int o0 = mt.o0, o1 = mt.o1;
+    const int i = wrap_idx(mt.i, nx, g.bc), tc = wrap_idx(mt.tc, nt, g.bc);
+    const bool active = mt.active;
     const long long N = g.N;
     const long long sd = (D == 1) ? (long long)nx : (long long)nx * g.n[1];
     const long long st = (TA == 1) ? (long long)nx : (long long)nx * g.n[1];
     const long long base = i + tc * st;
     const long long xp = wrap_idx(i + 1, nx, g.bc) - i;
-    const long long xm = wrap_idx(i - 1, nx, g.bc) - i;
-    const long long tp = (long long)(wrap_idx(tc + 1, nt, g.bc) - tc) * st;
-    const long long tm = (long long)(wrap_idx(tc - 1, nt, g.bc) - tc) * st;
-    const long long offEp = (E == 0) ? xp : tp, offEm = (E == 0) ? xm : tm;
-    const long long offFp = (F == 0) ? xp : tp, offFm = (F == 0) ? xm : tm;
+    const long long xm_ = wrap_idx(i - 1, nx, g.bc) - i;
+    const long long lo = (long long)(wrap_idx(mt.tc - 1, nt, g.bc) - tc) * st;
+    const long long hi = (long long)(wrap_idx(mt.tc + 1, nt, g.bc) - tc) * st;
     const T* rho = uf;
     const T* md = uf + (1 + D) * N;
     const T* BD = bin + D * N;
-    const T* BE = bin + E * N;
-    const T* BF = bin + F * N;
+    const T* BT = bin + (T_IS_E ? E : F) * N;
+    const T* BX = bin + (T_IS_E ? F : E) * N;
     const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
     const bool frozen = ctl->status != 0;
 
-    EmfPipe<T> e0, e1, f0, f1;
-    e0.clear();
-    e1.clear();
-    f0.clear();
-    f1.clear();
-    for (int h = o0 - GB; h <= o1 + GB - 1; ++h) {
+    auto load = [&](int h, CtLoad<T>& L) {
         const long long c = base + (long long)wrap_idx(h, nd, g.bc) * sd;
-        const T r0 = rho[c], m0 = md[c];
-        const T rEm = rho[c + offEm], mEm = md[c + offEm];
-        const T rEp = rho[c + offEp], mEp = md[c + offEp];
-        const T rFm = rho[c + offFm], mFm = md[c + offFm];
-        const T rFp = rho[c + offFp], mFp = md[c + offFp];
+        L.r0 = rho[c];
+        L.m0 = md[c];
+        L.bt = BT[c];
+        L.rTm = rho[c + lo];
+        L.mTm = md[c + lo];
+        L.rTp = rho[c + hi];
+        L.mTp = md[c + hi];
+        L.bt1 = BT[c + hi];
+        L.rXm = rho[c + xm_];
+        L.mXm = md[c + xm_];
+        L.rXp = rho[c + xp];
+        L.mXp = md[c + xp];
+        L.bx0 = BX[c];
+        L.bx1 = BX[c + xp];
+    };
+
+    EmfPipe<T> t0, t1, x0, x1;   // TA-face pencils (own, +TA), x-face pencils (own, +x)
+    t0.clear();
+    t1.clear();
+    x0.clear();
+    x1.clear();
+    CtLoad<T> cur;
+    load(o0 - GB, cur);
+    for (int h = o0 - GB; h <= o1 + GB - 1; ++h) {
+        CtLoad<T> nxt;
+        load(h + 1, nxt);
+        const T r0 = cur.r0, m0 = cur.m0;
+        const T rTm = cur.rTm, mTm = cur.mTm, rTp = cur.rTp, mTp = cur.mTp, bt1 = cur.bt1;
+        // original transverse faces of the output cell h - 4
+        const T bto = t0.B4, bxo = x0.B4;
         // face velocity along d on a transverse face: mass-weighted mean of the
         // two cells sharing it (Alg. 2 step 4)
-        const T Ge0 = e0.push((mEm + m0) / (rEm + r0), BE[c], dt);
-        const T Ge1 = e1.push((m0 + mEp) / (r0 + rEp), BE[c + offEp], dt);
-        const T Gf0 = f0.push((mFm + m0) / (rFm + r0), BF[c], dt);
-        const T Gf1 = f1.push((m0 + mFp) / (r0 + rFp), BF[c + offFp], dt);
+        const T Gt0 = t0.push((mTm + m0) / (rTm + r0), cur.bt, dt);
+        const T Gt1 = t1.push((m0 + mTp) / (r0 + rTp), bt1, dt);
+        const T Gx0 = x0.push((cur.mXm + m0) / (cur.rXm + r0), cur.bx0, dt);
+        const T Gx1 = x1.push((m0 + cur.mXp) / (r0 + cur.rXp), cur.bx1, dt);
         const int o = h - GB;
-        if (o >= o0) {
+        if (active && o >= o0) {
             const long long co = base + (long long)o * sd;
-            // e0.G5 etc. still hold the EMFs at edge o - 1/2 (updated below)
-            const T bd = BD[co], be = BE[co], bfv = BF[co];
+            // *.G5 still hold the EMFs at edge o - 1/2 (updated below)
+            const T bd = BD[co];
+            // e is the cyclic successor of d: the constraint adds the e
+            // contribution first
+            const T Ge0 = T_IS_E ? Gt0 : Gx0, Ge0p = T_IS_E ? t0.G5 : x0.G5, Ge1p = T_IS_E ? t1.G5 : x1.G5;
+            const T Gf0 = T_IS_E ? Gx0 : Gt0, Gf0p = T_IS_E ? x0.G5 : t0.G5, Gf1p = T_IS_E ? x1.G5 : t1.G5;
+            const T be = T_IS_E ? bto : bxo, bfv = T_IS_E ? bxo : bto;
             if (frozen) {
                 bout[E * N + co] = be;
                 bout[F * N + co] = bfv;
                 bout[D * N + co] = bd;
             } else {
-                bout[E * N + co] = be - dt * (Ge0 - e0.G5);
-                bout[F * N + co] = bfv - dt * (Gf0 - f0.G5);
-                bout[D * N + co] = (bd + dt * (e1.G5 - e0.G5)) + dt * (f1.G5 - f0.G5);
+                bout[E * N + co] = be - dt * (Ge0 - Ge0p);
+                bout[F * N + co] = bfv - dt * (Gf0 - Gf0p);
+                bout[D * N + co] = (bd + dt * (Ge1p - Ge0p)) + dt * (Gf1p - Gf0p);
             }
         }
-        e0.G5 = Ge0;
-        e1.G5 = Ge1;
-        f0.G5 = Gf0;
-        f1.G5 = Gf1;
+        t0.G5 = Gt0;
+        t1.G5 = Gt1;
+        x0.G5 = Gx0;
+        x1.G5 = Gx1;
+        cur = nxt;
     }
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(64 * MW) ct_march(const T* __restrict__ uf, const T* __restrict__ bin,
+                                                    T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
+                                                    double dt_arg, int chunk)
+{
+    const unsigned lb = blockIdx.x;
+    ct_march_body<T, D>(uf, bin, bout, g, ctl, dt_arg, chunk, lb);
 }
 
 // ---------------------------------------------------------------------------
 // fluid_x: one workgroup stages R rows x (S + 6) cells in LDS, one cell per
 // thread per pass (at most two passes), and updates S cells per row.
-constexpr int XT = 256;   // threads per workgroup of the x kernels
-constexpr int XP = 2;     // passes (cells per thread)
+// Workgroup shape of the x kernels: threads, and passes (cells per thread).
+// One pass of 320 threads covers a 256-cell row with its ghosts; FP32 fluid
+// sweeps measured faster with two passes of 256 threads.
+template <typename T, bool CT>
+constexpr int x_threads()
+{
+    return (kExact<T> || CT) ? 320 : 256;
+}
+template <typename T, bool CT>
+constexpr int x_passes()
+{
+    return (kExact<T> || CT) ? 1 : 2;
+}
 
 template <typename T, bool CFL>
-__global__ void __launch_bounds__(XT) fluid_x_lds(const T* __restrict__ uin, T* __restrict__ uout,
-                                                  const T* __restrict__ bf, Grid g, T gamma,
-                                                  const Ctl* __restrict__ ctl, double dt_arg, int S, int R,
-                                                  unsigned long long* __restrict__ parts)
+__device__ __forceinline__ void fluid_x_body(const T* __restrict__ uin, T* __restrict__ uout,
+                                             const T* __restrict__ bf, const Grid& g, T gamma,
+                                             const Ctl* __restrict__ ctl, double dt_arg, int S, int R, unsigned lb,
+                                             unsigned long long* __restrict__ part, T* sr)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* sr = reinterpret_cast<T*>(smem_raw);
+    constexpr int XT = x_threads<T, false>(), XP = x_passes<T, false>();
     const int Ext = S + 2 * GF;
     const int ncell = R * Ext;
     T* sl = sr + 5 * ncell;
@@ -527,7 +615,7 @@ __global__ void __launch_bounds__(XT) fluid_x_lds(const T* __restrict__ uin, T* 
     const long long nrows = (long long)ny * g.n[2];
     const long long N = g.N;
     const unsigned nseg = (nx + S - 1) / S;
-    const unsigned lb = blockIdx.x;   // segments fastest, then row groups
+    // segments fastest, then row groups
     const int o0 = (lb % nseg) * S;
     const long long row0 = (long long)(lb / nseg) * R;
     const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
@@ -653,19 +741,31 @@ __global__ void __launch_bounds__(XT) fluid_x_lds(const T* __restrict__ uin, T* 
             }
         }
     }
-    if constexpr (CFL) block_max_to_part<XT>(best, threadIdx.x, parts);
+    if constexpr (CFL) block_max_to_part<XT>(best, threadIdx.x, part);
+}
+
+template <typename T, bool CFL>
+__global__ void __launch_bounds__((x_threads<T, false>())) fluid_x_lds(const T* __restrict__ uin, T* __restrict__ uout,
+                                                  const T* __restrict__ bf, Grid g, T gamma,
+                                                  const Ctl* __restrict__ ctl, double dt_arg, int S, int R,
+                                                  unsigned long long* __restrict__ parts)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const unsigned lb = blockIdx.x;
+    fluid_x_body<T, CFL>(uin, uout, bf, g, gamma, ctl, dt_arg, S, R, lb, parts + blockIdx.x,
+                         reinterpret_cast<T*>(smem_raw));
 }
 
 // B_{y->x}, B_{z->x}: one workgroup stages R rows x (S + 8) cells in LDS and
 // runs the four EMF pencils of each row (own and +y for B_y, own and +z for
 // B_z) stage by stage.
 template <typename T>
-__global__ void __launch_bounds__(XT) ct_x_lds(const T* __restrict__ uf, const T* __restrict__ bin,
-                                               T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
-                                               double dt_arg, int S, int R)
+__device__ __forceinline__ void ct_x_body(const T* __restrict__ uf, const T* __restrict__ bin,
+                                          T* __restrict__ bout, const Grid& g, const Ctl* __restrict__ ctl,
+                                          double dt_arg, int S, int R, unsigned lb, T* sA)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* sA = reinterpret_cast<T*>(smem_raw);   // 4 x ncell: velocities, then v B^{t+dt/2}
+    constexpr int XT = x_threads<T, true>(), XP = x_passes<T, true>();
+    // sA: 4 x ncell: velocities, then v B^{t+dt/2}
     const int Ext = S + 2 * GB;
     const int ncell = R * Ext;
     T* sB = sA + 4 * ncell;                     // 4 x ncell: v B, then limited slopes
@@ -674,7 +774,7 @@ __global__ void __launch_bounds__(XT) ct_x_lds(const T* __restrict__ uf, const T
     const long long nrows = (long long)ny * nz;
     const long long N = g.N;
     const unsigned nseg = (nx + S - 1) / S;
-    const unsigned lb = blockIdx.x;   // segments fastest, then row groups
+    // segments fastest, then row groups
     const int o0 = (lb % nseg) * S;
     const long long row0 = (long long)(lb / nseg) * R;
     const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
@@ -836,20 +936,30 @@ __global__ void __launch_bounds__(XT) ct_x_lds(const T* __restrict__ uf, const T
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__((x_threads<T, true>())) ct_x_lds(const T* __restrict__ uf, const T* __restrict__ bin,
+                                               T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
+                                               double dt_arg, int S, int R)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const unsigned lb = blockIdx.x;
+    ct_x_body<T>(uf, bin, bout, g, ctl, dt_arg, S, R, lb, reinterpret_cast<T*>(smem_raw));
+}
+
 // ---------------------------------------------------------------------------
 constexpr int RB = 256;   // threads per block of the reductions
 
 // Per-cell CFL speed of eq. equat_CFL; per-block maxima into parts.
 template <typename T>
-__global__ void __launch_bounds__(RB) cfl_kernel(const T* __restrict__ u, const T* __restrict__ b, Grid g,
-                                                 T gamma, unsigned long long* __restrict__ parts)
+__device__ __forceinline__ void cfl_body(const T* __restrict__ u, const T* __restrict__ b, const Grid& g, T gamma,
+                                         unsigned lb, unsigned nb, unsigned long long* __restrict__ part)
 {
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const long long N = g.N;
     unsigned long long best = 0ull;
     // one x-row (j, k) per loop trip of a block, lanes along x
     const long long nrows = (long long)ny * nz;
-    for (long long row = blockIdx.x; row < nrows; row += gridDim.x) {
+    for (long long row = lb; row < nrows; row += nb) {
         const int j = (int)(row % ny), k = (int)(row / ny);
         const long long rb = row * nx;
         const long long yoff = (long long)(wrap_idx(j + 1, ny, g.bc) - j) * nx;
@@ -865,7 +975,14 @@ __global__ void __launch_bounds__(RB) cfl_kernel(const T* __restrict__ u, const 
             best = bits > best ? bits : best;
         }
     }
-    block_max_to_part<RB>(best, threadIdx.x, parts);
+    block_max_to_part<RB>(best, threadIdx.x, part);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RB) cfl_kernel(const T* __restrict__ u, const T* __restrict__ b, Grid g,
+                                                 T gamma, unsigned long long* __restrict__ parts)
+{
+    cfl_body<T>(u, b, g, gamma, blockIdx.x, gridDim.x, parts + blockIdx.x);
 }
 
 // max over cells of |div B| (cells whose upper faces are stored)
@@ -896,7 +1013,7 @@ __global__ void __launch_bounds__(RB) divb_kernel(const T* __restrict__ b, Grid 
         best = bits > best ? bits : best;
       }
     }
-    block_max_to_part<RB>(best, threadIdx.x, parts);
+    block_max_to_part<RB>(best, threadIdx.x, parts + blockIdx.x);
 }
 
 int reduce_blocks(const Grid& g)
@@ -926,11 +1043,10 @@ int march_chunk(const Grid& g, int d, int ghost)
 
 }  // namespace
 
-// one segment per row if it fits XT * XP cells, several rows per workgroup
-// when rows are short
-static void x_tile(const Grid& g, int ghost, int& S, int& R)
+// one segment per row if it fits cap = threads x passes cells, several rows
+// per workgroup when rows are short
+static void x_tile(const Grid& g, int ghost, int cap, int& S, int& R)
 {
-    const int cap = XT * XP;
     const int nx = g.n[0];
     int nseg = 1;
     while ((nx + nseg - 1) / nseg + 2 * ghost > cap) nseg++;
@@ -979,10 +1095,10 @@ static void fluid_launch(int axis, const T* u_in, T* u_out, const T* b, Grid g, 
     unsigned nb;
     if (axis == 0) {
         int S, R;
-        x_tile(g, GF, S, R);
+        x_tile(g, GF, x_threads<T, false>() * x_passes<T, false>(), S, R);
         nb = x_blocks(g, S, R);
         const size_t lds = sizeof(T) * 10 * (size_t)R * (S + 2 * GF);
-        hipLaunchKernelGGL((fluid_x_lds<T, CFL>), dim3(nb), dim3(XT), lds, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
+        hipLaunchKernelGGL((fluid_x_lds<T, CFL>), dim3(nb), dim3(x_threads<T, false>()), lds, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
                            S, R, parts);
     } else {
         const int chunk = march_chunk(g, axis, GF);
@@ -1015,9 +1131,9 @@ hipError_t launch_ct(int axis, const T* u, const T* b_in, T* b_out, Grid g, cons
 {
     if (axis == 0) {
         int S, R;
-        x_tile(g, GB, S, R);
+        x_tile(g, GB, x_threads<T, true>() * x_passes<T, true>(), S, R);
         const size_t lds = sizeof(T) * 12 * (size_t)R * (S + 2 * GB);
-        hipLaunchKernelGGL((ct_x_lds<T>), dim3(x_blocks(g, S, R)), dim3(XT), lds, s, u, b_in, b_out, g, ctl, dt, S,
+        hipLaunchKernelGGL((ct_x_lds<T>), dim3(x_blocks(g, S, R)), dim3(x_threads<T, true>()), lds, s, u, b_in, b_out, g, ctl, dt, S,
                            R);
     } else {
         const int chunk = march_chunk(g, axis, GB);
