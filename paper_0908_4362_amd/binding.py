@@ -1,4 +1,5 @@
-"""Thin ctypes binding of the C ABI in include/mhd.h (same names).
+"""Thin ctypes binding of the C ABI in include/mhd.h and include/mhd_batch.h
+(same names).
 
 Only argument marshalling lives here: every step of the computation runs in
 the HIP library. Host states are numpy arrays of shape (8, nz, ny, nx) (or any
@@ -59,6 +60,23 @@ def lib():
             "mhd_state_bytes": ([i, i, i, i], ctypes.c_size_t),
             "mhd_timing": ([vp, i], i),
             "mhd_timing_read": ([vp, i, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64)], i),
+            "mhd_batch_create": ([i, ctypes.POINTER(vp)], i),
+            "mhd_batch_destroy": ([vp], i),
+            "mhd_batch_set_stream": ([vp, vp], i),
+            "mhd_batch_problem_bytes": ([i, i, i, i], ctypes.c_size_t),
+            "mhd_batch_add": ([vp, i, i, i, d, i, vp, ctypes.POINTER(i)], i),
+            "mhd_batch_add_device": ([vp, i, i, i, d, i, vp, ctypes.POINTER(i)], i),
+            "mhd_batch_remove": ([vp, i], i),
+            "mhd_batch_count": ([vp, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_size_t)], i),
+            "mhd_batch_step": ([vp, i, d], i),
+            "mhd_batch_get_state": ([vp, i, vp], i),
+            "mhd_batch_get_state_device": ([vp, i, vp], i),
+            "mhd_batch_get_time": ([vp, i, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64)], i),
+            "mhd_batch_set_stop_time": ([vp, i, d], i),
+            "mhd_batch_status": ([vp, i], i),
+            "mhd_batch_set_graphs": ([vp, i], i),
+            "mhd_batch_autotune": ([vp, i], i),
+            "mhd_batch_tile": ([vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i)], i),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -179,6 +197,155 @@ def mhd_timing_read(h, kind: int):
     n = ctypes.c_int64()
     _check(lib().mhd_timing_read(h, kind, ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def mhd_batch_create(dtype: int):
+    h = ctypes.c_void_p()
+    _check(lib().mhd_batch_create(dtype, ctypes.byref(h)))
+    return h
+
+
+def mhd_batch_destroy(b):
+    _check(lib().mhd_batch_destroy(b))
+
+
+def mhd_batch_set_stream(b, stream):
+    ptr = None if stream is None else (stream if isinstance(stream, int) else int(stream.cuda_stream))
+    _check(lib().mhd_batch_set_stream(b, ptr))
+
+
+def mhd_batch_problem_bytes(nx: int, ny: int, nz: int, dtype: int) -> int:
+    return int(lib().mhd_batch_problem_bytes(nx, ny, nz, dtype))
+
+
+def mhd_batch_add(b, nx: int, ny: int, nz: int, gamma: float, bc: int, host_state: np.ndarray) -> int:
+    a = np.ascontiguousarray(host_state)
+    pid = ctypes.c_int()
+    _check(lib().mhd_batch_add(b, nx, ny, nz, gamma, bc, a.ctypes.data_as(ctypes.c_void_p), ctypes.byref(pid)))
+    return pid.value
+
+
+def mhd_batch_add_device(b, nx: int, ny: int, nz: int, gamma: float, bc: int, dev_state) -> int:
+    pid = ctypes.c_int()
+    _check(lib().mhd_batch_add_device(b, nx, ny, nz, gamma, bc, ctypes.c_void_p(_dev_ptr(dev_state)),
+                                      ctypes.byref(pid)))
+    return pid.value
+
+
+def mhd_batch_remove(b, pid: int):
+    _check(lib().mhd_batch_remove(b, pid))
+
+
+def mhd_batch_count(b):
+    n = ctypes.c_int()
+    nbytes = ctypes.c_size_t()
+    _check(lib().mhd_batch_count(b, ctypes.byref(n), ctypes.byref(nbytes)))
+    return n.value, nbytes.value
+
+
+def mhd_batch_step(b, n: int, cfl: float):
+    _check(lib().mhd_batch_step(b, n, cfl))
+
+
+def mhd_batch_get_state(b, pid: int, out: np.ndarray):
+    if not out.flags["C_CONTIGUOUS"]:
+        raise ValueError("output array must be C-contiguous")
+    _check(lib().mhd_batch_get_state(b, pid, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def mhd_batch_get_state_device(b, pid: int, dev_state):
+    _check(lib().mhd_batch_get_state_device(b, pid, ctypes.c_void_p(_dev_ptr(dev_state))))
+
+
+def mhd_batch_get_time(b, pid: int):
+    t = ctypes.c_double()
+    s = ctypes.c_int64()
+    _check(lib().mhd_batch_get_time(b, pid, ctypes.byref(t), ctypes.byref(s)))
+    return t.value, s.value
+
+
+def mhd_batch_set_stop_time(b, pid: int, t_stop):
+    _check(lib().mhd_batch_set_stop_time(b, pid, -1.0 if t_stop is None else float(t_stop)))
+
+
+def mhd_batch_status(b, pid: int) -> int:
+    """MHD_OK or MHD_ERR_NONFINITE; other errors raise."""
+    rc = lib().mhd_batch_status(b, pid)
+    if rc not in (MHD_OK, MHD_ERR_NONFINITE):
+        _check(rc)
+    return rc
+
+
+def mhd_batch_set_graphs(b, enable: bool):
+    _check(lib().mhd_batch_set_graphs(b, 1 if enable else 0))
+
+
+def mhd_batch_autotune(b, reps: int = 3):
+    _check(lib().mhd_batch_autotune(b, reps))
+
+
+def mhd_batch_tile(b, pid: int, kind: int):
+    p0 = ctypes.c_int()
+    p1 = ctypes.c_int()
+    _check(lib().mhd_batch_tile(b, pid, kind, ctypes.byref(p0), ctypes.byref(p1)))
+    return p0.value, p1.value
+
+
+class Batch:
+    """Owning wrapper of one batch (host-side convenience; no computation)."""
+
+    def __init__(self, dtype=MHD_F64):
+        self.dtype = dtype
+        self.np_dtype = _np_dtype(dtype)
+        self.shapes = {}
+        self.b = mhd_batch_create(dtype)
+
+    def close(self):
+        if self.b is not None:
+            mhd_batch_destroy(self.b)
+            self.b = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, state: np.ndarray, gamma: float, bc: int = MHD_BC_PERIODIC) -> int:
+        a = np.ascontiguousarray(state, dtype=self.np_dtype)
+        if a.ndim != 4 or a.shape[0] != 8:
+            raise ValueError("state must have shape (8, nz, ny, nx)")
+        nz, ny, nx = a.shape[1:]
+        pid = mhd_batch_add(self.b, nx, ny, nz, gamma, bc, a)
+        self.shapes[pid] = a.shape
+        return pid
+
+    def remove(self, pid: int):
+        mhd_batch_remove(self.b, pid)
+        self.shapes.pop(pid, None)
+
+    def step(self, n: int = 1, cfl: float = 0.7):
+        mhd_batch_step(self.b, n, cfl)
+
+    def get_state(self, pid: int) -> np.ndarray:
+        out = np.empty(self.shapes[pid], dtype=self.np_dtype)
+        return mhd_batch_get_state(self.b, pid, out)
+
+    def time(self, pid: int):
+        return mhd_batch_get_time(self.b, pid)
+
+    def status(self, pid: int) -> int:
+        return mhd_batch_status(self.b, pid)
+
+    def autotune(self, reps: int = 3):
+        mhd_batch_autotune(self.b, reps)
 
 
 class Solver:

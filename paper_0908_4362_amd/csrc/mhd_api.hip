@@ -207,6 +207,11 @@ int read_ctl(mhd_solver* h, Ctl* out)
 
 }  // namespace
 
+namespace mhd {
+int report(int code, const char* msg) { return fail(code, msg); }
+int report_hip(hipError_t e, const char* where) { return hip_fail(e, where); }
+}  // namespace mhd
+
 extern "C" {
 
 const char* mhd_last_error(void) { return g_err.c_str(); }

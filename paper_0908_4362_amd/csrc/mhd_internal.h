@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+#include <vector>
+
 namespace mhd {
 
 // Grid description passed by value to every kernel.
@@ -23,6 +26,11 @@ struct Ctl {
     int status;     // 0 ok, -4 non-finite c_max (latched)
     int pad;
 };
+
+// Error reporting of the C ABI: record a message for mhd_last_error() and
+// return code (report_hip: MHD_ERR_DEVICE with the HIP error text).
+int report(int code, const char* msg);
+int report_hip(hipError_t e, const char* where);
 
 // Grid-wide maxima are reduced in two levels: a producing kernel stores one
 // maximum per workgroup (ordered bit patterns of non-negative doubles) in a
@@ -49,5 +57,54 @@ hipError_t launch_fluid(int axis, const T* u_in, T* u_out, const T* b, Grid g, d
 template <typename T>
 hipError_t launch_ct(int axis, const T* u, const T* b_in, T* b_out, Grid g, const Ctl* ctl, double dt,
                      hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched launches: one launch runs one sub-operation for many independent
+// problems; workgroup w of the launch belongs to the problem whose range
+// [first, next first) holds w.
+
+// Launch kinds (numbered as the MHD_K_* timing kinds of the C ABI).
+enum { KIND_CFL = 0, KIND_FLUID_X, KIND_FLUID_Y, KIND_FLUID_Z, KIND_CT_X, KIND_CT_Y, KIND_CT_Z, KIND_COUNT };
+
+// One problem of a batch as the batched kernels see it.
+struct BJob {
+    void* u[2];                  // conserved fields, ping-pong copies (5 N elements each)
+    void* b[2];                  // face fields, ping-pong copies (3 N elements each)
+    Ctl* ctl;                    // the problem's control block (dt, t, stop time, status)
+    unsigned long long* parts;   // per-workgroup maxima of this problem
+    Grid g;
+    double gamma;
+};
+
+// Workgroups and tile parameters of one problem in one batched launch:
+// p0 = chunk length (y/z sweeps), segment length S (x sweeps) or workgroup
+// count (CFL); p1 = rows per workgroup (x sweeps).
+struct TileDesc {
+    unsigned first;
+    int p0, p1;
+    int pad;
+};
+
+// Tiles of one kind for a problem: the plain solver's choice, the
+// candidates the autotuner may time, workgroup count and LDS bytes.
+template <typename T>
+void tile_default(const Grid& g, int kind, int* p0, int* p1);
+template <typename T>
+void tile_candidates(const Grid& g, int kind, std::vector<std::pair<int, int>>& out);
+template <typename T>
+unsigned tile_blocks(const Grid& g, int kind, int p0, int p1);
+template <typename T>
+size_t tile_lds(int kind, int p0, int p1);
+
+// One batched sub-operation over njobs problems (tables in device memory,
+// nblocks = last first + last count). iu / ib select the ping-pong copies
+// read (the other copy is written). With cfl_parts a fluid sweep also stores
+// per-workgroup CFL maxima into each problem's parts.
+template <typename T>
+hipError_t launch_batch(int kind, bool cfl_parts, const BJob* jobs, const TileDesc* td, int njobs, unsigned nblocks,
+                        size_t lds, int iu, int ib, hipStream_t s);
+// Per-problem second level of the c_max reduction (td: the producing launch's
+// table) and the dt rule of each problem.
+hipError_t launch_finish_batch(const BJob* jobs, const TileDesc* td, int njobs, double cfl, hipStream_t s);
 
 }  // namespace mhd

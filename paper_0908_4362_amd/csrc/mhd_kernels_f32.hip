@@ -1,5 +1,5 @@
 // Single-precision instantiation of the step kernels (FMA contraction allowed).
-#include "mhd_kernels_impl.h"
+#include "mhd_batch_impl.h"
 
 namespace mhd {
 template hipError_t launch_cfl<float>(const float*, const float*, Grid, double, unsigned long long*, int*,
@@ -9,4 +9,10 @@ template hipError_t launch_fluid<float>(int, const float*, float*, const float*,
                                         unsigned long long*, int*, hipStream_t);
 template hipError_t launch_ct<float>(int, const float*, const float*, float*, Grid, const Ctl*, double,
                                      hipStream_t);
+template void tile_default<float>(const Grid&, int, int*, int*);
+template void tile_candidates<float>(const Grid&, int, std::vector<std::pair<int, int>>&);
+template unsigned tile_blocks<float>(const Grid&, int, int, int);
+template size_t tile_lds<float>(int, int, int);
+template hipError_t launch_batch<float>(int, bool, const BJob*, const TileDesc*, int, unsigned, size_t, int, int,
+                                         hipStream_t);
 }  // namespace mhd

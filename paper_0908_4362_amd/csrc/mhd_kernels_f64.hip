@@ -1,7 +1,7 @@
 // Double-precision instantiation of the step kernels, plus the
 // precision-independent launchers. Built with -ffp-contract=off: every FP64
 // expression rounds exactly as the CPU oracle's.
-#include "mhd_kernels_impl.h"
+#include "mhd_batch_impl.h"
 
 namespace mhd {
 namespace {
@@ -26,7 +26,33 @@ __global__ void __launch_bounds__(FB) finish_kernel(const unsigned long long* __
     }
 }
 
+// Batched second level: workgroup j reduces the maxima of problem j (as many
+// as the producing launch gave it workgroups) and applies its dt rule.
+constexpr int FBB = 256;
+__global__ void __launch_bounds__(FBB) finish_batch_kernel(const BJob* __restrict__ jobs,
+                                                           const TileDesc* __restrict__ td, double cfl)
+{
+    const int j = blockIdx.x;
+    const unsigned long long* parts = jobs[j].parts;
+    const unsigned n = td[j + 1].first - td[j].first;
+    unsigned long long best = 0ull;
+    for (unsigned k = threadIdx.x; k < n; k += FBB) best = parts[k] > best ? parts[k] : best;
+    best = block_max_u64<FBB>(best, threadIdx.x);
+    if (threadIdx.x == 0) {
+        Ctl* ctl = jobs[j].ctl;
+        ctl->cmax = __longlong_as_double((long long)best);
+        if (cfl > 0.0) apply_dt_rule(ctl, cfl);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_finish_batch(const BJob* jobs, const TileDesc* td, int njobs, double cfl, hipStream_t s)
+{
+    if (njobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(finish_batch_kernel, dim3(njobs), dim3(FBB), 0, s, jobs, td, cfl);
+    return hipGetLastError();
+}
 
 hipError_t launch_finish(const unsigned long long* parts, int nparts, int what, double cfl, Ctl* ctl, hipStream_t s)
 {
@@ -55,4 +81,10 @@ template hipError_t launch_fluid<double>(int, const double*, double*, const doub
                                          double, unsigned long long*, int*, hipStream_t);
 template hipError_t launch_ct<double>(int, const double*, const double*, double*, Grid, const Ctl*, double,
                                       hipStream_t);
+template void tile_default<double>(const Grid&, int, int*, int*);
+template void tile_candidates<double>(const Grid&, int, std::vector<std::pair<int, int>>&);
+template unsigned tile_blocks<double>(const Grid&, int, int, int);
+template size_t tile_lds<double>(int, int, int);
+template hipError_t launch_batch<double>(int, bool, const BJob*, const TileDesc*, int, unsigned, size_t, int, int,
+                                         hipStream_t);
 }  // namespace mhd

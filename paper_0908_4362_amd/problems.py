@@ -262,3 +262,69 @@ def random_smooth(nx, ny, nz, seed, gamma=5.0 / 3.0, amp=0.2, modes=3, bmean=(0.
     bcy = bmean[1] + d(0, 2) - d(2, 0)
     bcz = bmean[2] + d(1, 0) - d(0, 1)
     return assemble(rho, vel, p, bface, (bcx, bcy, bcz), gamma, shape)
+
+
+# --------------------------------------------------------------------------
+# Batched workload: many periodic linear Alfven waves of uneven sizes
+# --------------------------------------------------------------------------
+
+BATCH_SIZES = (32, 48, 64, 96, 128)
+
+
+def alfven_batch_specs(count: int, seed: int = MASTER_SEED + 400, sizes=BATCH_SIZES, gamma: float = 5.0 / 3.0):
+    """Seeded parameters of `count` Alfven-wave problems: cubic grid n drawn
+    uniformly from `sizes`, unit background field along a uniformly random
+    direction b (redrawn while |k.b| < 0.1 or |k x b| < 0.1 for the wave
+    normal k = (1,1,1)/sqrt3, so the wave neither stalls nor degenerates) and
+    amplitude uniform in [1e-4, 1e-2]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    khat = np.ones(3) / math.sqrt(3.0)
+    specs = []
+    for _ in range(count):
+        n = int(rng.choice(np.asarray(sizes)))
+        while True:
+            b = rng.normal(size=3)
+            b /= np.linalg.norm(b)
+            if abs(float(khat @ b)) >= 0.1 and np.linalg.norm(np.cross(khat, b)) >= 0.1:
+                break
+        amp = float(rng.uniform(1e-4, 1e-2))
+        specs.append({"n": n, "b0": tuple(float(c) for c in b), "amp": amp, "gamma": gamma})
+    return specs
+
+
+def alfven_111(n: int, b0, amp: float, gamma: float = 5.0 / 3.0, rho0: float = 1.0, dtype=np.float64):
+    """Linear Alfven wave with wave vector 2 pi (1,1,1) on a periodic n^3 unit
+    box: rho = rho0, p = 1/gamma, background field b0, field perturbation amp
+    along n = k x b0 (unit), velocity -sign(k.b0) amp n / sqrt(rho0); the face
+    field is the discrete curl of the edge potential (k x n) amp / |k| cos(k.x).
+
+    Every quantity depends on the cell position only through m = i + j + k, so
+    it is tabulated over m (3n - 2 values) and gathered; this is the same state
+    linear_wave builds, without evaluating sin/cos at every cell."""
+    b0 = np.asarray(b0, dtype=np.float64)
+    khat = np.ones(3) / math.sqrt(3.0)
+    ndir = np.cross(khat, b0)
+    ndir /= np.linalg.norm(ndir)
+    sgn = 1.0 if float(khat @ b0) >= 0.0 else -1.0
+    h = 1.0 / n
+    kn = 2.0 * math.pi * math.sqrt(3.0)
+    w = np.cross(khat, ndir) * (amp / kn)
+    m = np.arange(3 * n - 2, dtype=np.float64)
+    sn = np.sin(2.0 * math.pi * h * (m + 1.5))                                    # cell centres
+    dc = (np.cos(2.0 * math.pi * h * (m + 1.5)) - np.cos(2.0 * math.pi * h * (m + 0.5))) / h   # edge differences
+    idx = (np.arange(n)[None, None, :] + np.arange(n)[None, :, None] + np.arange(n)[:, None, None])
+    p0 = 1.0 / gamma
+    s = np.empty((8, n, n, n), dtype=dtype)
+    dv = -sgn * amp / math.sqrt(rho0) * ndir
+    bc = [b0[a] + amp * ndir[a] * sn for a in range(3)]
+    mom = [rho0 * dv[a] * sn for a in range(3)]
+    kin = 0.5 * rho0 * ((dv[0] * sn) ** 2 + (dv[1] * sn) ** 2 + (dv[2] * sn) ** 2)
+    mag = 0.5 * (bc[0] ** 2 + bc[1] ** 2 + bc[2] ** 2)
+    s[0] = rho0
+    for a in range(3):
+        s[1 + a] = np.take(mom[a], idx)
+    s[4] = np.take(p0 / (gamma - 1.0) + kin + mag, idx)
+    curl = (w[2] - w[1], w[0] - w[2], w[1] - w[0])
+    for a in range(3):
+        s[5 + a] = np.take(b0[a] + curl[a] * dc, idx)
+    return s

@@ -1,9 +1,10 @@
 """CPU checks of the C ABI boundary: the built library loads, exports every
-function include/mhd.h declares, and rejects bad arguments before touching a
-device. No compute call is made here."""
+function the headers under include/ declare, and rejects bad arguments before
+touching a device. No compute call is made here."""
 from __future__ import annotations
 
 import ctypes
+import glob
 import os
 import re
 import subprocess
@@ -11,13 +12,15 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "mhd.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**\s*(mhd_\w+)\s*\(", text, flags=re.M)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**\s*(mhd_\w+)\s*\(", text, flags=re.M))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -31,9 +34,10 @@ def libmhd():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for n in ("mhd_create", "mhd_set_state", "mhd_step", "mhd_get_state", "mhd_divb_max", "mhd_destroy"):
+    for n in ("mhd_create", "mhd_set_state", "mhd_step", "mhd_get_state", "mhd_divb_max", "mhd_destroy",
+              "mhd_batch_create", "mhd_batch_add", "mhd_batch_step", "mhd_batch_get_state", "mhd_batch_autotune"):
         assert n in names
-    assert len(names) >= 18
+    assert len(names) >= 35
 
 
 def test_library_exports_every_declared_symbol(libmhd):
@@ -74,3 +78,25 @@ def test_argument_errors_are_reported_before_device_use(libmhd):
     assert B.mhd_state_bytes(0, 1, 1, B.MHD_F32) == 0
     assert B.mhd_state_bytes(4, 4, 4, B.MHD_F32) >= 2 * 8 * 64 * 4
     assert h.value is None
+
+
+def test_batch_argument_errors_are_reported_before_device_use(libmhd):
+    B = libmhd
+    L = B.lib()
+    out = ctypes.c_void_p()
+    assert L.mhd_batch_create(7, ctypes.byref(out)) == B.MHD_ERR_ARG and out.value is None
+    assert L.mhd_batch_create(B.MHD_F64, None) == B.MHD_ERR_ARG
+    assert L.mhd_batch_destroy(None) == B.MHD_OK
+    pid = ctypes.c_int()
+    assert L.mhd_batch_add(None, 4, 4, 4, 1.4, 0, None, ctypes.byref(pid)) == B.MHD_ERR_ARG
+    assert L.mhd_batch_step(None, 1, 0.7) == B.MHD_ERR_ARG
+    assert L.mhd_batch_remove(None, 1) == B.MHD_ERR_ARG
+    assert L.mhd_batch_status(None, 1) == B.MHD_ERR_ARG
+    assert L.mhd_batch_autotune(None, 1) == B.MHD_ERR_ARG
+    assert B.mhd_batch_problem_bytes(0, 4, 4, B.MHD_F64) == 0
+    assert B.mhd_batch_problem_bytes(4, 4, 4, 3) == 0
+    # two state copies of 8 fields, control block and reduction slots
+    for (nx, ny, nz) in ((32, 32, 32), (48, 20, 7), (128, 1, 1)):
+        for dt, es in ((B.MHD_F32, 4), (B.MHD_F64, 8)):
+            nbytes = B.mhd_batch_problem_bytes(nx, ny, nz, dt)
+            assert 16 * nx * ny * nz * es < nbytes < 16 * nx * ny * nz * es + 6 * 256 + 8 * 65536

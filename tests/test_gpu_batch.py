@@ -1,0 +1,224 @@
+"""GPU checks of batched solves (include/mhd_batch.h): every problem of a
+batch must come out bitwise equal to a plain single-problem solve of the same
+input and step count (the batched launches run the same kernel bodies), for
+uneven grid sizes, both boundary conditions, both precisions, problems added
+and removed between steps (cohorts in different sweep orders), graph replay,
+autotuned tiles and a problem that fails alone. FP64 problems are also held
+to the oracle gate (relative L-infinity <= 1e-10 per field)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_0908_4362_amd import problems as P
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+F64_STEP_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0908_4362_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def note(msg):
+    print("[gpu] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def plain(B, s, gamma, bc, dtype, nsteps, cfl=0.7, t_stop=None):
+    nz, ny, nx = s.shape[1:]
+    with B.Solver(nx, ny, nz, gamma, bc, dtype) as sv:
+        sv.set_state(s)
+        if t_stop is not None:
+            B.mhd_set_stop_time(sv.h, t_stop)
+        if nsteps:
+            sv.step(nsteps, cfl)
+        return sv.get_state(), sv.time()
+
+
+def mixed_problems():
+    """(state, gamma, bc): uneven sizes spanning several tiles and ragged
+    tails, 1D / 2D / 3D, periodic and outflow, smooth and shocked."""
+    seed = P.MASTER_SEED + 300
+    return [
+        (P.random_smooth(24, 20, 18, seed=seed), H.GAMMA53, 0),
+        (P.random_smooth(33, 26, 20, seed=seed + 1), H.GAMMA53, 1),
+        (P.blast(16), H.GAMMA53, 0),
+        (P.random_smooth(70, 12, 9, seed=seed + 2), H.GAMMA53, 0),
+        (P.brio_wu(96), 2.0, 1),
+        (P.orszag_tang(32), H.GAMMA53, 0),
+        (P.random_smooth(9, 67, 5, seed=seed + 3), 1.4, 1),
+    ]
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_batch_equals_plain_bitwise(B, dtype):
+    probs = mixed_problems()
+    note("batch of %d problems, dtype %d" % (len(probs), dtype))
+    with B.Batch(dtype) as bt:
+        ids = [bt.add(s, gm, bc) for (s, gm, bc) in probs]
+        bt.step(5)
+        for pid, (s, gm, bc) in zip(ids, probs):
+            want, tw = plain(B, s, gm, bc, dtype, 5)
+            got = bt.get_state(pid)
+            assert np.array_equal(got, want), (pid, s.shape)
+            assert bt.time(pid) == tw
+            assert bt.status(pid) == B.MHD_OK
+
+
+def test_batch_fp64_matches_oracle(B, orc):
+    probs = mixed_problems()[:3]
+    note("batch vs oracle")
+    with B.Batch(B.MHD_F64) as bt:
+        ids = [bt.add(s, gm, bc) for (s, gm, bc) in probs]
+        bt.step(10)
+        for pid, (s, gm, bc) in zip(ids, probs):
+            nz, ny, nx = s.shape[1:]
+            want, _, _ = orc.run(orc.Grid(nx, ny, nz, gm, bc), s, 10, 0.7)
+            got = bt.get_state(pid)
+            for f in range(8):
+                assert H.rel_linf(got[f], want[f]) <= F64_STEP_TOL, (pid, f)
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_batch_staggered_admission(B, graphs):
+    """Problems join and leave between steps; those that joined at different
+    steps run different sweep orders in the same batched step."""
+    seed = P.MASTER_SEED + 310
+    a = P.random_smooth(20, 18, 16, seed=seed)
+    b = P.random_smooth(28, 14, 22, seed=seed + 1)
+    c = P.blast(20)
+    d = P.random_smooth(17, 23, 11, seed=seed + 2)
+    note("staggered admission, graphs %s" % graphs)
+    with B.Batch(B.MHD_F64) as bt:
+        B.mhd_batch_set_graphs(bt.b, graphs)
+        ia = bt.add(a, H.GAMMA53, 0)
+        bt.step(2)
+        ib = bt.add(b, H.GAMMA53, 1)
+        bt.step(3)
+        assert np.array_equal(bt.get_state(ia), plain(B, a, H.GAMMA53, 0, 1, 5)[0])
+        bt.remove(ia)
+        ic = bt.add(c, H.GAMMA53, 0)
+        bt.step(1)
+        idd = bt.add(d, 1.4, 0)
+        bt.step(4)
+        assert B.mhd_batch_count(bt.b)[0] == 3
+        for pid, (s, gm, bc, n) in ((ib, (b, H.GAMMA53, 1, 8)), (ic, (c, H.GAMMA53, 0, 5)), (idd, (d, 1.4, 0, 4))):
+            want, tw = plain(B, s, gm, bc, 1, n)
+            assert bt.time(pid)[1] == n
+            assert np.array_equal(bt.get_state(pid), want), pid
+            assert bt.time(pid) == tw
+
+
+def test_batch_graph_replay_equals_eager(B):
+    probs = mixed_problems()
+    note("graph replay vs eager")
+    out = []
+    for graphs in (True, False):
+        with B.Batch(B.MHD_F32) as bt:
+            B.mhd_batch_set_graphs(bt.b, graphs)
+            ids = [bt.add(s, gm, bc) for (s, gm, bc) in probs]
+            for _ in range(7):   # every sweep order replayed at least twice
+                bt.step(1)
+            out.append([bt.get_state(pid) for pid in ids])
+    for g, e in zip(*out):
+        assert np.array_equal(g, e)
+
+
+def test_batch_autotune_keeps_results(B):
+    probs = mixed_problems()
+    note("autotune")
+    with B.Batch(B.MHD_F64) as bt:
+        ids = [bt.add(s, gm, bc) for (s, gm, bc) in probs]
+        bt.step(2)
+        bt.autotune(2)
+        for pid, (s, gm, bc) in zip(ids, probs):
+            nz, ny, nx = s.shape[1:]
+            for kind in range(1, B.MHD_K_COUNT):
+                p0, p1 = B.mhd_batch_tile(bt.b, pid, kind)
+                assert p0 >= 1
+                if kind in (B.MHD_K_FLUID_X, B.MHD_K_CT_X):
+                    assert 1 <= p1 <= ny * nz and p0 <= nx
+                else:
+                    axis = 1 if kind in (B.MHD_K_FLUID_Y, B.MHD_K_CT_Y) else 2
+                    assert p0 <= s.shape[3 - axis]
+        bt.step(3)
+        for pid, (s, gm, bc) in zip(ids, probs):
+            assert np.array_equal(bt.get_state(pid), plain(B, s, gm, bc, 1, 5)[0]), pid
+
+
+def test_batch_failure_is_isolated(B):
+    seed = P.MASTER_SEED + 320
+    good = P.random_smooth(22, 19, 13, seed=seed)
+    bad = P.random_smooth(18, 18, 18, seed=seed + 1)
+    bad[0, 3, 4, 5] = np.nan
+    note("failure isolation")
+    with B.Batch(B.MHD_F64) as bt:
+        ig = bt.add(good, H.GAMMA53, 0)
+        ib = bt.add(bad, H.GAMMA53, 0)
+        bt.step(3)
+        assert bt.status(ib) == B.MHD_ERR_NONFINITE
+        assert np.array_equal(bt.get_state(ib), bad, equal_nan=True)
+        assert bt.status(ig) == B.MHD_OK
+        assert np.array_equal(bt.get_state(ig), plain(B, good, H.GAMMA53, 0, 1, 3)[0])
+
+
+def test_batch_stop_time_per_problem(B):
+    s1 = P.brio_wu(128)
+    s2 = P.random_smooth(16, 16, 16, seed=P.MASTER_SEED + 330)
+    note("per-problem stop time")
+    with B.Batch(B.MHD_F64) as bt:
+        i1 = bt.add(s1, 2.0, 1)
+        i2 = bt.add(s2, H.GAMMA53, 0)
+        B.mhd_batch_set_stop_time(bt.b, i1, 5.5)
+        bt.step(60)
+        assert bt.time(i1)[0] == 5.5
+        want, tw = plain(B, s1, 2.0, 1, 1, 60, t_stop=5.5)
+        assert np.array_equal(bt.get_state(i1), want)
+        assert bt.time(i2) == plain(B, s2, H.GAMMA53, 0, 1, 60)[1]
+
+
+def test_batch_device_input_equals_host_input(B):
+    import torch
+
+    s = P.random_smooth(30, 22, 18, seed=P.MASTER_SEED + 340)
+    dev = torch.from_numpy(s).cuda()
+    torch.cuda.synchronize()
+    note("device input")
+    with B.Batch(B.MHD_F64) as bt:
+        i1 = B.mhd_batch_add_device(bt.b, 30, 22, 18, H.GAMMA53, 0, dev)
+        bt.shapes[i1] = s.shape
+        i2 = bt.add(s, H.GAMMA53, 0)
+        bt.step(2)
+        out = torch.empty_like(dev)
+        B.mhd_batch_get_state_device(bt.b, i1, out)
+        got = bt.get_state(i2)
+        assert np.array_equal(bt.get_state(i1), got)
+        torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), got)
+
+
+def test_batch_argument_errors(B):
+    with B.Batch(B.MHD_F64) as bt:
+        with pytest.raises(B.MHDError) as ei:
+            B.mhd_batch_add(bt.b, 0, 4, 4, 1.4, 0, np.zeros(8))
+        assert ei.value.code == B.MHD_ERR_ARG
+        with pytest.raises(B.MHDError):
+            B.mhd_batch_remove(bt.b, 12345)
+        with pytest.raises(B.MHDError):
+            B.mhd_batch_step(bt.b, 1, 1.5)
+        with pytest.raises(B.MHDError):
+            B.mhd_batch_autotune(bt.b, 0)
+        bt.step(2)   # an empty batch steps nothing
