@@ -10,8 +10,16 @@ in HBM before the timed region; the whole step runs in the HIP library.
 
 Prints one JSON line: cell-updates/s per full step (FP64 headline, FP32 next
 to it), the roofline of the dominant kernel from HIP events recorded on the
-handle's stream during the timed region, and the CPU oracle timed on a bounded
-sample of the same workload.
+handle's stream during the timed region, the CPU oracle timed on a bounded
+sample of the same workload, and the batched workload (many periodic linear
+Alfven waves of sizes drawn from {32, 48, 64, 96, 128}^3, FP32, advanced
+together by the batch runtime) against looping the plain solver over the same
+problems, with a bitwise comparison of every final state; and the serving
+workload (seeded requests for blast waves and extruded Orszag-Tang vortices of
+32^3 to 192^3 cells, FP32 or FP64, 100 steps each, Poisson arrivals at
+fractions of the measured saturation rate, admitted under an HBM budget)
+against a first-come first-served queue of plain solves with the same
+arrivals.
 """
 from __future__ import annotations
 
@@ -116,6 +124,231 @@ def roofline(kern, ncell, esize, n):
     }
 
 
+def run_batched(B, P, count, steps, warmup, dtype, tune_reps):
+    """The batched workload: every problem advanced `warmup` + `steps` full steps by one batch, then
+    by its own plain solver; the timed regions are the `steps` steps of each."""
+    import numpy as np
+    import torch
+
+    specs = P.alfven_batch_specs(count)
+    npd = np.float64 if dtype == B.MHD_F64 else np.float32
+    tdt = torch.float64 if dtype == B.MHD_F64 else torch.float32
+
+    def state(sp):
+        return P.alfven_111(sp["n"], sp["b0"], sp["amp"], sp["gamma"], dtype=npd)
+
+    cells = sum(sp["n"] ** 3 for sp in specs)
+    t0 = time.perf_counter()
+    bt = B.Batch(dtype)
+    ids = [bt.add(state(sp), sp["gamma"], B.MHD_BC_PERIODIC) for sp in specs]
+    setup_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    if tune_reps:
+        bt.autotune(tune_reps)
+    tune_s = time.perf_counter() - t0
+    bt.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.step(steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    print("bench: batched %d problems, %d cells: %.3f s for %d steps" % (count, cells, t_batch, steps),
+          file=sys.stderr, flush=True)
+    t_plain, same = 0.0, 0
+    for sp, pid in zip(specs, ids):
+        n = sp["n"]
+        with B.Solver(n, n, n, sp["gamma"], B.MHD_BC_PERIODIC, dtype) as sv:
+            sv.set_state(state(sp))
+            sv.step(warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sv.step(steps)
+            torch.cuda.synchronize()
+            t_plain += time.perf_counter() - t0
+            a = torch.empty(8 * n ** 3, dtype=tdt, device="cuda")
+            b = torch.empty_like(a)
+            B.mhd_get_state_device(sv.h, a)
+            B.mhd_batch_get_state_device(bt.b, pid, b)
+            torch.cuda.synchronize()
+            same += int(torch.equal(a, b))
+    bt.close()
+    return {
+        "workload": "%d periodic linear Alfven waves, n^3 with n drawn from {32,48,64,96,128}, %s, CFL 0.7"
+                    % (count, "FP64" if dtype == B.MHD_F64 else "FP32"),
+        "problems": count,
+        "cells": cells,
+        "steps": steps,
+        "warmup": warmup,
+        "value": round(cells * steps / t_batch, 1),
+        "unit": "cell-updates/s",
+        "ms_per_step": round(t_batch * 1e3 / steps, 3),
+        "plain_loop_value": round(cells * steps / t_plain, 1),
+        "speedup_vs_plain_loop": round(t_plain / t_batch, 3),
+        "identical_to_plain": same,
+        "graphs": True,
+        "autotune_reps": tune_reps,
+        "setup_s": round(setup_s, 2),
+        "autotune_s": round(tune_s, 2),
+    }
+
+
+class _Producer:
+    """Builds request states in arrival order on a few host threads, a bounded
+    number ahead of the consumer (numpy releases the GIL for the bulk work)."""
+
+    def __init__(self, P, specs, ahead=16, workers=4):
+        from collections import deque
+        from concurrent.futures import ThreadPoolExecutor
+
+        import numpy as np
+
+        self.pool = ThreadPoolExecutor(max_workers=workers)
+        self.specs = specs
+        self.make = lambda sp: P.serving_state(sp, np.float64 if sp["dtype"] == 1 else np.float32)
+        self.window = deque()
+        self.k = 0
+        for _ in range(min(ahead, len(specs))):
+            self._push()
+
+    def _push(self):
+        if self.k < len(self.specs):
+            self.window.append(self.pool.submit(self.make, self.specs[self.k]))
+            self.k += 1
+
+    def ready(self):
+        return bool(self.window) and self.window[0].done()
+
+    def next(self):
+        st = self.window.popleft().result()
+        self._push()
+        if not self.window:
+            self.pool.shutdown(wait=False)
+        return st
+
+
+def _pct(xs, q):
+    import numpy as np
+
+    return round(float(np.percentile(np.asarray(xs), q)), 4)
+
+
+def serve_once(B, P, specs, arrivals, budget):
+    """Open-loop run: request i arrives at arrivals[i] seconds after the start; returns
+    (latencies, makespan, late submissions)."""
+    n = len(specs)
+    prod = _Producer(P, specs)
+    lat = [0.0] * n
+    idx = {}
+    late = 0
+    with B.Server(budget) as srv:
+        t0 = B.mhd_server_now()
+        nxt = done = 0
+        running = queued = 0
+        last = t0
+        while done < n:
+            now = B.mhd_server_now() - t0
+            while nxt < n and arrivals[nxt] <= now:
+                if not prod.ready() and (running or queued):
+                    break      # keep the device busy; submit when the state is built
+                sp = specs[nxt]
+                st = prod.next()
+                if B.mhd_server_now() - t0 > arrivals[nxt] + 0.05:
+                    late += 1
+                rid = srv.submit(st, sp["gamma"], B.MHD_BC_PERIODIC, sp["dtype"], sp["nsteps"])
+                idx[rid] = nxt
+                nxt += 1
+                now = B.mhd_server_now() - t0
+            if nxt > done:     # submitted requests not yet finished (queued, running or to retire)
+                running, queued = srv.tick()
+            for rid in srv.finished():
+                info = srv.info(rid)
+                if info["status"] != B.MHD_OK:
+                    raise RuntimeError("request %d failed with status %d" % (rid, info["status"]))
+                i = idx.pop(rid)
+                lat[i] = info["t_finish"] - (t0 + arrivals[i])
+                last = max(last, info["t_finish"])
+                srv.meta.pop(rid, None)
+                B.mhd_server_take(srv.s, rid, _scratch(specs[i]))
+                done += 1
+                if done % 16 == 0 or done == n:
+                    print("bench: served %d/%d (%.2f s)" % (done, n, B.mhd_server_now() - t0), file=sys.stderr,
+                          flush=True)
+            if nxt == done and nxt < n:
+                wait = arrivals[nxt] - (B.mhd_server_now() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.005))
+    return lat, last - t0, late
+
+
+_scratch_bufs = {}
+
+
+def _scratch(sp):
+    import numpy as np
+
+    key = (sp["n"], sp["dtype"])
+    if key not in _scratch_bufs:
+        _scratch_bufs[key] = np.empty((8, sp["n"], sp["n"], sp["n"]),
+                                      dtype=np.float64 if sp["dtype"] == 1 else np.float32)
+    return _scratch_bufs[key]
+
+
+def run_serving(B, P, count, fracs, budget, steps):
+    import numpy as np
+    import torch
+
+    specs = P.serving_specs(count, nsteps=steps)
+    work = [sp["n"] ** 3 * sp["nsteps"] for sp in specs]
+    # plain solves one at a time: the service time of each request alone
+    prod = _Producer(P, specs)
+    service = []
+    for sp in specs:
+        st = prod.next()
+        n = sp["n"]
+        with B.Solver(n, n, n, sp["gamma"], B.MHD_BC_PERIODIC, sp["dtype"]) as sv:
+            sv.set_state(st)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sv.step(sp["nsteps"], 0.7)
+            service.append(time.perf_counter() - t0)
+    print("bench: serving, plain solves %.2f s" % sum(service), file=sys.stderr, flush=True)
+    # saturation: every request present at the start
+    lat0, span0, _ = serve_once(B, P, specs, [0.0] * count, budget)
+    sat = count / span0
+    print("bench: serving, saturation %.2f requests/s" % sat, file=sys.stderr, flush=True)
+    rng = np.random.Generator(np.random.PCG64(P.MASTER_SEED + 501))
+    gaps = rng.exponential(1.0, size=count)
+    points = []
+    for f in fracs:
+        lam = f * sat
+        arr = list(np.cumsum(gaps / lam) - gaps[0] / lam)
+        lat, span, late = serve_once(B, P, specs, arr, budget)
+        # the same arrivals served first come, first served by plain solves
+        fin, slat = 0.0, []
+        for a, sv in zip(arr, service):
+            fin = max(a, fin) + sv
+            slat.append(fin - a)
+        points.append({"rate_frac": f, "rate_rps": round(lam, 3), "p50_s": _pct(lat, 50), "p99_s": _pct(lat, 99),
+                       "cell_updates_per_s": round(sum(work) / span, 1), "late_submissions": late,
+                       "plain_fcfs_p50_s": _pct(slat, 50), "plain_fcfs_p99_s": _pct(slat, 99)})
+        print("bench: serving at %.2f x saturation: p50 %.3f s p99 %.3f s" % (f, points[-1]["p50_s"],
+              points[-1]["p99_s"]), file=sys.stderr, flush=True)
+    return {
+        "workload": "%d requests: blast / extruded Orszag-Tang, n^3 with n in {32..192}, FP32/FP64, %d steps, "
+                    "Poisson arrivals" % (count, steps),
+        "requests": count,
+        "hbm_budget_bytes": budget,
+        "cell_updates": sum(work),
+        "saturation_rps": round(sat, 3),
+        "saturation_cell_updates_per_s": round(sum(work) / span0, 1),
+        "saturation_p50_s": _pct(lat0, 50),
+        "saturation_p99_s": _pct(lat0, 99),
+        "plain_serial_cell_updates_per_s": round(sum(work) / sum(service), 1),
+        "speedup_vs_plain_serial": round(sum(service) / span0, 3),
+        "points": points,
+    }
+
+
 def cpu_baseline(P, n, sample):
     """The oracle, single thread, on a bounded sample: one full step of a
     sample^3 box cut from the centre of the n^3 blast (outflow edges)."""
@@ -155,6 +388,15 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=96, help="edge of the box timed on the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=50)
+    ap.add_argument("--batch-tune", type=int, default=3, help="autotuner launches per candidate (0: off)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serve-count", type=int, default=96)
+    ap.add_argument("--serve-rates", default="0.5,1.0", help="arrival rates as fractions of saturation")
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--serve-steps", type=int, default=100)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM counters)")
     args = ap.parse_args()
@@ -219,6 +461,13 @@ def main():
             "effective_step_bandwidth_GBs": round(STEP_WORDS * 4 * ncell * args.steps / sec32 / 1e9, 1),
             "kernels_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in kern32.items()},
         }
+    if not args.no_batch:
+        print("bench: batched workload", file=sys.stderr, flush=True)
+        out["batched"] = run_batched(B, P, args.batch_count, args.batch_steps, 2, B.MHD_F32, args.batch_tune)
+    if not args.no_serve:
+        print("bench: serving workload", file=sys.stderr, flush=True)
+        out["serving"] = run_serving(B, P, args.serve_count, [float(x) for x in args.serve_rates.split(",")],
+                                     int(args.serve_budget_gb * (1 << 30)), args.serve_steps)
     if rank == 0 and not args.no_cpu_baseline:
         print("bench: cpu oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(P, n, args.cpu_sample)

@@ -146,6 +146,31 @@ int mhd_timing_read(mhd_t* h, int kind, double* total_ms, int64_t* launches);
 /* Number of device bytes a handle of this size holds. */
 size_t mhd_state_bytes(int nx, int ny, int nz, int dtype);
 
+/* Headless diagnostics: the derived fields one would render (the paper shows
+ * density, gas pressure and field images, Sec. 4.4 and Sec. 5), computed on
+ * the device from the current state with the centred field of eq. equat_b
+ * averaged from the two faces of each cell:
+ *   MHD_D_PRESSURE           p = (gamma - 1)(E - rho v^2 / 2 - b^2 / 2)
+ *   MHD_D_MAGNETIC_PRESSURE  b^2 / 2
+ *   MHD_D_SPEED              |v|
+ *   MHD_D_DIVB               sum over d of B_d(upper face) - B_d(lower face)
+ *                            (faces beyond the edge through the boundary map)
+ *   MHD_D_CFL_SPEED          max_d |v_d| + sqrt(|gamma p + b^2| / rho)
+ * axis < 0: the whole grid, nx*ny*nz values in the state's cell order;
+ * axis = 0, 1 or 2: the plane x, y or z = index (0 <= index < n_axis), in the
+ * cell order of the two remaining axes (the lower-numbered one fastest).
+ * dev_out: device buffer of the handle's dtype, written asynchronously on the
+ * handle's stream. */
+enum {
+    MHD_D_PRESSURE = 0,
+    MHD_D_MAGNETIC_PRESSURE = 1,
+    MHD_D_SPEED = 2,
+    MHD_D_DIVB = 3,
+    MHD_D_CFL_SPEED = 4,
+    MHD_D_COUNT = 5
+};
+int mhd_diagnostic(mhd_t* h, int kind, int axis, int index, void* dev_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,5 +1,5 @@
-"""Thin ctypes binding of the C ABI in include/mhd.h and include/mhd_batch.h
-(same names).
+"""Thin ctypes binding of the C ABI in include/mhd.h, include/mhd_batch.h and
+include/mhd_server.h (same names).
 
 Only argument marshalling lives here: every step of the computation runs in
 the HIP library. Host states are numpy arrays of shape (8, nz, ny, nx) (or any
@@ -21,6 +21,7 @@ MHD_BC_PERIODIC, MHD_BC_OUTFLOW = 0, 1
 MHD_F32, MHD_F64 = 0, 1
 MHD_K_CFL, MHD_K_FLUID_X, MHD_K_FLUID_Y, MHD_K_FLUID_Z, MHD_K_CT_X, MHD_K_CT_Y, MHD_K_CT_Z, MHD_K_COUNT = range(8)
 KERNEL_KINDS = ("cfl", "fluid_x", "fluid_y", "fluid_z", "ct_x", "ct_y", "ct_z")
+MHD_D_PRESSURE, MHD_D_MAGNETIC_PRESSURE, MHD_D_SPEED, MHD_D_DIVB, MHD_D_CFL_SPEED, MHD_D_COUNT = range(6)
 
 _lib = None
 
@@ -60,6 +61,7 @@ def lib():
             "mhd_state_bytes": ([i, i, i, i], ctypes.c_size_t),
             "mhd_timing": ([vp, i], i),
             "mhd_timing_read": ([vp, i, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64)], i),
+            "mhd_diagnostic": ([vp, i, i, i, vp], i),
             "mhd_batch_create": ([i, ctypes.POINTER(vp)], i),
             "mhd_batch_destroy": ([vp], i),
             "mhd_batch_set_stream": ([vp, vp], i),
@@ -77,6 +79,16 @@ def lib():
             "mhd_batch_set_graphs": ([vp, i], i),
             "mhd_batch_autotune": ([vp, i], i),
             "mhd_batch_tile": ([vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i)], i),
+            "mhd_server_now": ([], d),
+            "mhd_server_create": ([ctypes.c_size_t, d, ctypes.POINTER(vp)], i),
+            "mhd_server_destroy": ([vp], i),
+            "mhd_server_submit": ([vp, i, i, i, d, i, i, vp, i, ctypes.POINTER(i)], i),
+            "mhd_server_tick": ([vp, ctypes.POINTER(i), ctypes.POINTER(i)], i),
+            "mhd_server_poll": ([vp, ctypes.POINTER(i)], i),
+            "mhd_server_info": ([vp, i, ctypes.POINTER(i), ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(i), ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d)], i),
+            "mhd_server_take": ([vp, i, vp], i),
+            "mhd_server_stats": ([vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int64)], i),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -199,6 +211,11 @@ def mhd_timing_read(h, kind: int):
     return ms.value, n.value
 
 
+def mhd_diagnostic(h, kind: int, axis: int, index: int, dev_out):
+    """dev_out: a torch tensor on the GPU (or a raw device address) with room for the field."""
+    _check(lib().mhd_diagnostic(h, kind, axis, index, ctypes.c_void_p(_dev_ptr(dev_out))))
+
+
 def mhd_batch_create(dtype: int):
     h = ctypes.c_void_p()
     _check(lib().mhd_batch_create(dtype, ctypes.byref(h)))
@@ -290,6 +307,120 @@ def mhd_batch_tile(b, pid: int, kind: int):
     p1 = ctypes.c_int()
     _check(lib().mhd_batch_tile(b, pid, kind, ctypes.byref(p0), ctypes.byref(p1)))
     return p0.value, p1.value
+
+
+MHD_REQ_QUEUED, MHD_REQ_RUNNING, MHD_REQ_DONE = 0, 1, 2
+
+
+def mhd_server_now() -> float:
+    return float(lib().mhd_server_now())
+
+
+def mhd_server_create(hbm_budget: int, cfl: float):
+    h = ctypes.c_void_p()
+    _check(lib().mhd_server_create(int(hbm_budget), cfl, ctypes.byref(h)))
+    return h
+
+
+def mhd_server_destroy(s):
+    _check(lib().mhd_server_destroy(s))
+
+
+def mhd_server_submit(s, nx: int, ny: int, nz: int, gamma: float, bc: int, dtype: int, host_state: np.ndarray,
+                      nsteps: int) -> int:
+    a = np.ascontiguousarray(host_state, dtype=_np_dtype(dtype))
+    rid = ctypes.c_int()
+    _check(lib().mhd_server_submit(s, nx, ny, nz, gamma, bc, dtype, a.ctypes.data_as(ctypes.c_void_p), nsteps,
+                                   ctypes.byref(rid)))
+    return rid.value
+
+
+def mhd_server_tick(s):
+    running = ctypes.c_int()
+    queued = ctypes.c_int()
+    _check(lib().mhd_server_tick(s, ctypes.byref(running), ctypes.byref(queued)))
+    return running.value, queued.value
+
+
+def mhd_server_poll(s) -> int:
+    rid = ctypes.c_int()
+    _check(lib().mhd_server_poll(s, ctypes.byref(rid)))
+    return rid.value
+
+
+def mhd_server_info(s, rid: int) -> dict:
+    st, status = ctypes.c_int(), ctypes.c_int()
+    t, ta, tb, tc = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().mhd_server_info(s, rid, ctypes.byref(st), ctypes.byref(t), ctypes.byref(n), ctypes.byref(status),
+                                 ctypes.byref(ta), ctypes.byref(tb), ctypes.byref(tc)))
+    return {"state": st.value, "t_sim": t.value, "steps": n.value, "status": status.value, "t_submit": ta.value,
+            "t_admit": tb.value, "t_finish": tc.value}
+
+
+def mhd_server_take(s, rid: int, out: np.ndarray):
+    if not out.flags["C_CONTIGUOUS"]:
+        raise ValueError("output array must be C-contiguous")
+    _check(lib().mhd_server_take(s, rid, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def mhd_server_stats(s):
+    nbytes = ctypes.c_size_t()
+    cu = ctypes.c_int64()
+    _check(lib().mhd_server_stats(s, ctypes.byref(nbytes), ctypes.byref(cu)))
+    return nbytes.value, cu.value
+
+
+class Server:
+    """Owning wrapper of one request server (host-side convenience; no computation)."""
+
+    def __init__(self, hbm_budget: int, cfl: float = 0.7):
+        self.s = mhd_server_create(hbm_budget, cfl)
+        self.meta = {}
+
+    def close(self):
+        if self.s is not None:
+            mhd_server_destroy(self.s)
+            self.s = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, state: np.ndarray, gamma: float, bc: int, dtype: int, nsteps: int) -> int:
+        nz, ny, nx = state.shape[1:]
+        rid = mhd_server_submit(self.s, nx, ny, nz, gamma, bc, dtype, state, nsteps)
+        self.meta[rid] = (state.shape, dtype)
+        return rid
+
+    def tick(self):
+        return mhd_server_tick(self.s)
+
+    def finished(self):
+        """Ids of requests finished since the last call."""
+        out = []
+        while True:
+            rid = mhd_server_poll(self.s)
+            if rid < 0:
+                return out
+            out.append(rid)
+
+    def info(self, rid: int) -> dict:
+        return mhd_server_info(self.s, rid)
+
+    def take(self, rid: int) -> np.ndarray:
+        shape, dtype = self.meta.pop(rid)
+        out = np.empty(shape, dtype=_np_dtype(dtype))
+        return mhd_server_take(self.s, rid, out)
 
 
 class Batch:

@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libmhd.so")
 # (source, extra flags): the FP64 kernels are built without FMA contraction so
 # that they round exactly as the CPU oracle does
 SOURCES = [("mhd_kernels_f64.hip", ["-ffp-contract=off"]), ("mhd_kernels_f32.hip", []), ("mhd_api.hip", []),
-           ("mhd_batch.hip", [])]
+           ("mhd_batch.hip", []), ("mhd_server.hip", [])]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are kept out of the device code: the compiler may

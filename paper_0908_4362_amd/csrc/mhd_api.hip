@@ -508,6 +508,26 @@ int mhd_step_dt(mhd_t* h, double dt, int64_t s_order)
     return h->dtype == MHD_F64 ? sweeps<double>(h, s_order, dt, false) : sweeps<float>(h, s_order, dt, false);
 }
 
+int mhd_diagnostic(mhd_t* h, int kind, int axis, int index, void* dev_out)
+{
+    if (int rc = check(h)) return rc;
+    if (kind < 0 || kind >= MHD_D_COUNT) return fail(MHD_ERR_ARG, "unknown diagnostic");
+    if (axis > 2) return fail(MHD_ERR_ARG, "axis must be < 0 (whole grid), 0, 1 or 2");
+    if (axis >= 0 && (index < 0 || index >= h->g.n[axis])) return fail(MHD_ERR_ARG, "plane index out of range");
+    if (!dev_out) return fail(MHD_ERR_ARG, "null output pointer");
+    if (int rc = set_current(h)) return rc;
+    const int ax = axis < 0 ? -1 : axis;
+    hipError_t e = h->dtype == MHD_F64
+                       ? mhd::launch_diag<double>(static_cast<const double*>(h->u[h->ucur]),
+                                                  static_cast<const double*>(h->b[h->bcur]), h->g, h->gamma, kind, ax,
+                                                  index, static_cast<double*>(dev_out), h->stream)
+                       : mhd::launch_diag<float>(static_cast<const float*>(h->u[h->ucur]),
+                                                 static_cast<const float*>(h->b[h->bcur]), h->g, h->gamma, kind, ax,
+                                                 index, static_cast<float*>(dev_out), h->stream);
+    if (e != hipSuccess) return hip_fail(e, "diagnostic launch");
+    return MHD_OK;
+}
+
 static int collect_timing(mhd_t* h)
 {
     HIPCHK(hipStreamSynchronize(h->stream), "stream sync");

@@ -107,4 +107,12 @@ hipError_t launch_batch(int kind, bool cfl_parts, const BJob* jobs, const TileDe
 // table) and the dt rule of each problem.
 hipError_t launch_finish_batch(const BJob* jobs, const TileDesc* td, int njobs, double cfl, hipStream_t s);
 
+// Derived field `kind` (0 gas pressure, 1 magnetic pressure, 2 speed, 3 cell
+// divergence of B, 4 CFL speed) for the whole grid (axis < 0, N values) or
+// for the plane axis = index (values in the order of the two other axes, the
+// lower one fastest), into out.
+template <typename T>
+hipError_t launch_diag(const T* u, const T* b, Grid g, double gamma, int kind, int axis, int index, T* out,
+                       hipStream_t s);
+
 }  // namespace mhd

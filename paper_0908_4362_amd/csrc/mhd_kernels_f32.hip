@@ -1,5 +1,6 @@
 // Single-precision instantiation of the step kernels (FMA contraction allowed).
 #include "mhd_batch_impl.h"
+#include "mhd_diag_impl.h"
 
 namespace mhd {
 template hipError_t launch_cfl<float>(const float*, const float*, Grid, double, unsigned long long*, int*,
@@ -15,4 +16,5 @@ template unsigned tile_blocks<float>(const Grid&, int, int, int);
 template size_t tile_lds<float>(int, int, int);
 template hipError_t launch_batch<float>(int, bool, const BJob*, const TileDesc*, int, unsigned, size_t, int, int,
                                          hipStream_t);
+template hipError_t launch_diag<float>(const float*, const float*, Grid, double, int, int, int, float*, hipStream_t);
 }  // namespace mhd

@@ -2,6 +2,7 @@
 // precision-independent launchers. Built with -ffp-contract=off: every FP64
 // expression rounds exactly as the CPU oracle's.
 #include "mhd_batch_impl.h"
+#include "mhd_diag_impl.h"
 
 namespace mhd {
 namespace {
@@ -87,4 +88,5 @@ template unsigned tile_blocks<double>(const Grid&, int, int, int);
 template size_t tile_lds<double>(int, int, int);
 template hipError_t launch_batch<double>(int, bool, const BJob*, const TileDesc*, int, unsigned, size_t, int, int,
                                          hipStream_t);
+template hipError_t launch_diag<double>(const double*, const double*, Grid, double, int, int, int, double*, hipStream_t);
 }  // namespace mhd

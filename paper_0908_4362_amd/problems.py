@@ -156,6 +156,69 @@ def blast(n: int, p_in: float = 10.0, p_out: float = 0.1, radius: float = 0.1,
     return assemble(1.0, (0.0, 0.0, 0.0), p, b, b, gamma, shape)
 
 
+def dai_woodward(n: int, axis: int = 0, ntrans: int = 1, gamma: float = 5.0 / 3.0):
+    """MHD shock tube of Sec. 5.1.2 (Dai and Woodward) along `axis`: left
+    (cell centre < 0.5) rho 1.08, p 0.95, v = (1.2, 0.01, 0.5), B = (2, 3.6, 2)
+    / sqrt(4 pi); right rho 1, p 1, v = 0, B = (2, 4, 2) / sqrt(4 pi). The
+    normal field is read as 2 / sqrt(4 pi), like the transverse ones (the
+    printed 2 sqrt(4 pi) is taken as a typo). Components are given along the
+    tube (normal first, then the two transverse axes in cyclic order)."""
+    shape_xyz = [ntrans, ntrans, ntrans]
+    shape_xyz[axis] = n
+    nx, ny, nz = shape_xyz
+    shape = (nz, ny, nx)
+    pos = (np.arange(n) + 0.5) / n
+    sel = [None, None, None]
+    sel[2 - axis] = slice(None)
+    L = (pos < 0.5)[tuple(sel)]
+    q = 1.0 / math.sqrt(4.0 * math.pi)
+    left_v, right_v = (1.2, 0.01, 0.5), (0.0, 0.0, 0.0)
+    left_b, right_b = (2.0 * q, 3.6 * q, 2.0 * q), (2.0 * q, 4.0 * q, 2.0 * q)
+    vel = [None] * 3
+    bfield = [None] * 3
+    for k in range(3):
+        a = (axis + k) % 3
+        vel[a] = np.broadcast_to(np.where(L, left_v[k], right_v[k]), shape).astype(np.float64)
+        bfield[a] = np.broadcast_to(np.where(L, left_b[k], right_b[k]), shape).astype(np.float64)
+    rho = np.where(L, 1.08, 1.0)
+    p = np.where(L, 0.95, 1.0)
+    return assemble(rho, tuple(vel), p, tuple(bfield), tuple(bfield), gamma, shape)
+
+
+def blast2d(n: int, gamma: float = 5.0 / 3.0):
+    """2D blast wave of Sec. 5.2.2 on n x n: rho 1, v 0, B = (1, 1, 0) / sqrt2,
+    p 10 inside r < 0.1 about (0.5, 0.5), 0.1 outside (the second pressure
+    printed with the other constants is taken as a stray)."""
+    return blast(n, nz=1, gamma=gamma)
+
+
+ROTORS = {1: {"v0": 2.0, "p": 1.0, "gamma": 1.4, "bx": 5.0, "t_max": 0.15},
+          2: {"v0": 1.0, "p": 0.5, "gamma": 5.0 / 3.0, "bx": 2.5, "t_max": 0.295}}
+
+
+def rotor(n: int, which: int = 1):
+    """MHD rotor of Sec. 5.2.3 on n x n: dense disk (rho 10) of radius 0.1
+    spinning rigidly with speed v0 at its edge, a taper to the ambient rho 1
+    at rest between r 0.1 and 0.115 with f = (0.115 - r) / 0.015,
+    rho = 1 + 9 f and v = f v0 (-(y - 0.5), (x - 0.5)) / r (the taper's v_y
+    sign is read as that of the disk, which keeps v continuous at r = 0.1),
+    uniform p and B = (bx / sqrt(4 pi), 0, 0). Parameter set `which` = 1 or 2."""
+    c = ROTORS[which]
+    shape = (1, n, n)
+    x, y, _ = _grid(n, n, 1, "ccc")
+    dx, dy = x - 0.5, y - 0.5
+    r = np.sqrt(dx * dx + dy * dy) + 0.0 * (x + y)
+    r0, r1 = 0.1, 0.115
+    f = (r1 - r) / (r1 - r0)
+    inside, taper = r < r0, (r >= r0) & (r < r1)
+    rho = np.where(inside, 10.0, np.where(taper, 1.0 + 9.0 * f, 1.0))
+    rs = np.where(r > 0.0, r, 1.0)
+    vx = np.where(inside, -c["v0"] * dy / r0, np.where(taper, -f * c["v0"] * dy / rs, 0.0))
+    vy = np.where(inside, c["v0"] * dx / r0, np.where(taper, f * c["v0"] * dx / rs, 0.0))
+    b = (np.full(shape, c["bx"] / math.sqrt(4.0 * math.pi)), np.zeros(shape), np.zeros(shape))
+    return assemble(rho, (vx, vy, 0.0), c["p"], b, b, c["gamma"], shape)
+
+
 # --------------------------------------------------------------------------
 # Smooth states with known behaviour
 # --------------------------------------------------------------------------
@@ -327,4 +390,76 @@ def alfven_111(n: int, b0, amp: float, gamma: float = 5.0 / 3.0, rho0: float = 1
     curl = (w[2] - w[1], w[0] - w[2], w[1] - w[0])
     for a in range(3):
         s[5 + a] = np.take(b0[a] + curl[a] * dc, idx)
+    return s
+
+
+# --------------------------------------------------------------------------
+# Serving workload: blast waves and extruded Orszag-Tang vortices
+# --------------------------------------------------------------------------
+
+SERVE_SIZES = (32, 64, 96, 128, 160, 192)
+
+
+def serving_specs(count: int, seed: int = MASTER_SEED + 500, sizes=SERVE_SIZES, nsteps: int = 100):
+    """Seeded request parameters: half 3D blast waves (ambient p 0.1, p_in
+    uniform in [1, 100], radius uniform in [0.05, 0.15], uniform field of
+    magnitude uniform in [0, 1] along a uniformly random direction), half
+    Orszag-Tang vortices extruded along z; cubic grid n drawn from `sizes`;
+    FP32 or FP64 with equal probability; `nsteps` full steps each."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    specs = []
+    for _ in range(count):
+        kind = "blast" if rng.uniform() < 0.5 else "vortex"
+        n = int(rng.choice(np.asarray(sizes)))
+        dtype = 1 if rng.uniform() < 0.5 else 0
+        sp = {"kind": kind, "n": n, "dtype": dtype, "nsteps": nsteps, "gamma": 5.0 / 3.0}
+        if kind == "blast":
+            d = rng.normal(size=3)
+            d /= np.linalg.norm(d)
+            bmag = float(rng.uniform(0.0, 1.0))
+            sp.update(p_in=float(rng.uniform(1.0, 100.0)), radius=float(rng.uniform(0.05, 0.15)),
+                      bvec=tuple(float(c) for c in bmag * d))
+        specs.append(sp)
+    return specs
+
+
+def serving_state(sp: dict, dtype=np.float64):
+    """Initial state of one serving request, written straight into an array of
+    `dtype`: the same values as blast(n, p_in, 0.1, radius, bvec) or
+    orszag_tang(n, nz=n), built from 1D / 2D factors instead of full-size
+    temporaries."""
+    n, gamma = sp["n"], sp["gamma"]
+    h = 1.0 / n
+    s = np.empty((8, n, n, n), dtype=dtype)
+    c = (np.arange(n) + 0.5) * h
+    if sp["kind"] == "blast":
+        bv = sp["bvec"]
+        mag = 0.5 * (bv[0] ** 2 + bv[1] ** 2 + bv[2] ** 2)
+        e_in = sp["p_in"] / (gamma - 1.0) + 0.0 + mag
+        e_out = 0.1 / (gamma - 1.0) + 0.0 + mag
+        d2 = (c - 0.5) ** 2
+        r2 = (d2[None, None, :] + d2[None, :, None]) + d2[:, None, None]
+        s[0] = 1.0
+        s[1:4] = 0.0
+        s[4] = np.where(r2 < sp["radius"] ** 2, e_in, e_out)
+        for a in range(3):
+            s[5 + a] = bv[a]
+        return s
+    b0 = 1.0 / math.sqrt(4.0 * math.pi)
+    rho = 25.0 / (36.0 * math.pi)
+    p = 5.0 / (12.0 * math.pi)
+    vx = -np.sin(2 * math.pi * c)[:, None] + 0.0 * c[None, :]    # (y, x)
+    vy = np.sin(2 * math.pi * c)[None, :] + 0.0 * c[:, None]
+    bx = -b0 * np.sin(2 * math.pi * c)[:, None] + 0.0 * c[None, :]
+    by = b0 * np.sin(4 * math.pi * c)[None, :] + 0.0 * c[:, None]
+    kin = 0.5 * rho * (vx ** 2 + vy ** 2 + 0.0 ** 2)
+    mag = 0.5 * (bx ** 2 + by ** 2 + 0.0 ** 2)
+    s[0] = rho
+    s[1] = (rho * vx)[None]
+    s[2] = (rho * vy)[None]
+    s[3] = 0.0
+    s[4] = (p / (gamma - 1.0) + kin + mag)[None]
+    s[5] = bx[None]
+    s[6] = by[None]
+    s[7] = 0.0
     return s

@@ -55,3 +55,28 @@ def test_alfven_111_field_is_divergence_free_and_eigenvector():
     kh = 2.0 * math.pi / n
     assert np.linalg.norm(v + sg * db) <= kh * kh * np.linalg.norm(v)
     assert abs(v @ khat) <= 1e-15 and abs(v @ b0) <= 1e-15
+
+
+def test_serving_specs_follow_the_recipe():
+    specs = P.serving_specs(400)
+    assert specs == P.serving_specs(400)
+    kinds = [sp["kind"] for sp in specs]
+    assert 150 < kinds.count("blast") < 250
+    assert 150 < sum(sp["dtype"] for sp in specs) < 250
+    assert set(sp["n"] for sp in specs) == set(P.SERVE_SIZES)
+    for sp in specs:
+        assert sp["nsteps"] == 100
+        if sp["kind"] == "blast":
+            assert 1.0 <= sp["p_in"] <= 100.0 and 0.05 <= sp["radius"] <= 0.15
+            assert np.linalg.norm(sp["bvec"]) <= 1.0
+
+
+def test_serving_state_equals_the_paper_problem_generators():
+    for sp in P.serving_specs(12, seed=3, sizes=(8, 12, 20)):
+        n = sp["n"]
+        if sp["kind"] == "blast":
+            ref = P.blast(n, p_in=sp["p_in"], p_out=0.1, radius=sp["radius"], bvec=sp["bvec"])
+        else:
+            ref = P.orszag_tang(n, nz=n)
+        assert np.array_equal(P.serving_state(sp), ref)
+        assert np.array_equal(P.serving_state(sp, np.float32), ref.astype(np.float32))

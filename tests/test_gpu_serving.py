@@ -1,0 +1,119 @@
+"""GPU checks of the request server (include/mhd_server.h): continuous
+batching of mixed FP32/FP64 requests under an HBM budget. Every served result
+must equal the same request solved alone by a plain handle (bitwise: the
+server runs the same kernels), whatever ran beside it; admission respects the
+budget and arrival order; failures stay with their request."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_0908_4362_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0908_4362_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def note(msg):
+    print("[gpu] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def alone(B, state, gamma, bc, dtype, nsteps):
+    nz, ny, nx = state.shape[1:]
+    with B.Solver(nx, ny, nz, gamma, bc, dtype) as sv:
+        sv.set_state(state)
+        sv.step(nsteps, 0.7)
+        return sv.get_state(), sv.time()
+
+
+def small_requests():
+    specs = P.serving_specs(10, seed=P.MASTER_SEED + 600, sizes=(12, 16, 24, 28), nsteps=1)
+    out = []
+    for k, sp in enumerate(specs):
+        npd = np.float64 if sp["dtype"] == 1 else np.float32
+        out.append((P.serving_state(sp, npd), sp["gamma"], k % 2, sp["dtype"], 4 + (k * 3) % 9))
+    return out
+
+
+def test_served_results_equal_alone_under_a_tight_budget(B):
+    reqs = small_requests()
+    sizes = sorted(B.mhd_batch_problem_bytes(*r[0].shape[:0:-1], r[3]) for r in reqs)
+    budget = sum(sizes[-3:])          # at most about three requests resident at once
+    note("serving %d requests, budget %d bytes" % (len(reqs), budget))
+    with B.Server(budget) as srv:
+        ids = {}
+        results = {}
+        order = []
+        k = 0
+        ticks = 0
+        while len(results) < len(reqs):
+            # two arrivals every third tick: later requests join while earlier ones run
+            if k < len(reqs) and ticks % 3 == 0:
+                for _ in range(2):
+                    if k < len(reqs):
+                        st, gm, bc, dt, ns = reqs[k]
+                        ids[srv.submit(st, gm, bc, dt, ns)] = k
+                        k += 1
+            srv.tick()
+            used, _ = B.mhd_server_stats(srv.s)
+            assert used <= budget
+            ticks += 1
+            for rid in srv.finished():
+                info = srv.info(rid)
+                assert info["status"] == B.MHD_OK
+                assert info["t_submit"] <= info["t_admit"] <= info["t_finish"]
+                order.append((info["t_admit"], ids[rid]))
+                results[ids[rid]] = (srv.take(rid), info)
+            assert ticks < 1000
+    # first come, first served: admission follows submission order
+    adm = [i for _, i in sorted(order)]
+    assert adm == sorted(adm)
+    for i, (st, gm, bc, dt, ns) in enumerate(reqs):
+        got, info = results[i]
+        want, (t, s) = alone(B, st, gm, bc, dt, ns)
+        assert info["steps"] == ns == s
+        assert info["t_sim"] == t
+        assert np.array_equal(got, want), i
+
+
+def test_oversized_request_is_rejected(B):
+    st = P.serving_state(P.serving_specs(1, sizes=(16,))[0])
+    with B.Server(4096) as srv:
+        with pytest.raises(B.MHDError) as ei:
+            srv.submit(st, 5.0 / 3.0, 0, B.MHD_F64, 3)
+        assert ei.value.code == B.MHD_ERR_ARG
+        with pytest.raises(B.MHDError):
+            srv.submit(st, 5.0 / 3.0, 0, B.MHD_F64, 0)
+
+
+def test_failed_request_does_not_disturb_the_others(B):
+    good = P.random_smooth(20, 16, 12, seed=P.MASTER_SEED + 610)
+    bad = P.random_smooth(14, 14, 14, seed=P.MASTER_SEED + 611)
+    bad[0, 2, 3, 4] = np.nan           # c_max turns NaN
+    note("serving failure isolation")
+    with B.Server(1 << 30) as srv:
+        rg = srv.submit(good, 5.0 / 3.0, 0, B.MHD_F64, 6)
+        rb = srv.submit(bad, 5.0 / 3.0, 0, B.MHD_F64, 6)
+        done = {}
+        for _ in range(20):
+            srv.tick()
+            for rid in srv.finished():
+                done[rid] = (srv.info(rid), srv.take(rid))
+        assert set(done) == {rg, rb}
+        assert done[rb][0]["status"] == B.MHD_ERR_NONFINITE
+        assert done[rg][0]["status"] == B.MHD_OK
+        assert np.array_equal(done[rg][1], alone(B, good, 5.0 / 3.0, 0, B.MHD_F64, 6)[0])
