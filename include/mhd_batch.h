@@ -19,10 +19,11 @@
  * shape (chunk length along the sweep for y/z sweeps, rows per workgroup for
  * x sweeps) that runs fastest on the device; tiles never change results.
  *
- * Memory: each problem owns one device allocation of
+ * Memory: each problem lives in one device block of
  * mhd_batch_problem_bytes(nx, ny, nz, dtype) bytes (two state copies, its
- * control block and reduction slots), made when it is added and released when
- * it is removed. The batch owns its own stream (default priority) unless
+ * control block and reduction slots), allocated when it is added and
+ * released when it is removed, or provided by the caller
+ * (mhd_batch_add_inplace). The batch owns its own stream (default priority) unless
  * mhd_batch_set_stream gives another. Return codes and mhd_last_error() are
  * those of mhd.h. A batch is not thread-safe.
  */
@@ -64,7 +65,30 @@ int mhd_batch_add(mhd_batch_t* b, int nx, int ny, int nz, double gamma, int bc, 
 int mhd_batch_add_device(mhd_batch_t* b, int nx, int ny, int nz, double gamma, int bc, const void* dev_state,
                          int* id);
 
-/* Remove a problem and release its memory (waits for the batch's stream). */
+/* Byte offsets, within a problem's device block, of state copy 0 of the
+ * conserved fields (5 fields of nx*ny*nz elements), of the face fields
+ * (3 fields) and of the control block, and the block size (as
+ * mhd_batch_problem_bytes). */
+int mhd_batch_problem_layout(int nx, int ny, int nz, int dtype, size_t* off_u0, size_t* off_b0, size_t* off_ctl,
+                             size_t* bytes);
+
+/* Add a problem in a caller-owned device block of mhd_batch_problem_bytes
+ * bytes whose copy-0 regions (mhd_batch_problem_layout) hold, or will hold,
+ * the initial state: ready (a hipEvent_t, or null) marks the point after
+ * which they do, and the batch's stream waits for it. Nothing is copied and
+ * the host does not wait. The caller keeps the block: after
+ * mhd_batch_remove it may reuse it once the batch's stream has passed the
+ * removal (mhd_batch_record an event and wait for it). */
+int mhd_batch_add_inplace(mhd_batch_t* b, int nx, int ny, int nz, double gamma, int bc, void* dev_block, void* ready,
+                          int* id);
+
+/* Record a HIP event (hipEvent_t as void*) on the batch's stream after all
+ * work issued so far. */
+int mhd_batch_record(mhd_batch_t* b, void* event);
+
+/* Remove a problem. Memory the batch allocated is released (waiting for the
+ * batch's stream); a caller-owned block is left to the caller, without
+ * waiting. Between steps the problem's state is in its copy-0 regions. */
 int mhd_batch_remove(mhd_batch_t* b, int id);
 
 /* Number of problems and device bytes they hold. */

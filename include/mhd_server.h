@@ -9,9 +9,11 @@
  * finishes. Each tick advances every admitted request by one full step: FP32
  * and FP64 requests run as two batches (include/mhd_batch.h) on two streams,
  * so their work overlaps, and requests admitted at different ticks share the
- * batched launches of their sweep order. A request that reaches its step
- * count is retired at the next tick: its state is copied to host memory, its
- * device memory is released, and it joins the completion queue.
+ * batched launches of their sweep order. Initial and final states move
+ * between pinned host memory and the device on a third stream, overlapping
+ * the steps; a request that reaches its step count leaves its batch at the
+ * next tick and joins the completion queue once its final state is on the
+ * host. Device blocks and pinned buffers are reused across requests.
  *
  * Each request is advanced by exactly the arithmetic of a plain solve
  * (mhd_step), so its result is bitwise the result of solving it alone.
@@ -50,10 +52,14 @@ int mhd_server_destroy(mhd_server_t* s);
 int mhd_server_submit(mhd_server_t* s, int nx, int ny, int nz, double gamma, int bc, int dtype,
                       const void* host_state, int nsteps, int* req);
 
-/* One scheduling round: retire requests that have taken all their steps,
- * admit queued requests in arrival order while they fit the budget, then
- * issue one full step of every admitted request (asynchronous). *running and
- * *queued (optional) receive the counts after the round. */
+/* One scheduling round: finish requests whose final state has reached the
+ * host, send requests that have taken all their steps out of their batch
+ * (their state follows asynchronously), admit queued requests in arrival
+ * order while they fit the budget, then issue one full step of every
+ * admitted request (asynchronous; the host stays at most two rounds ahead of
+ * the device). A round with nothing to step waits for the oldest pending
+ * copy-out. *running (admitted, including those whose state is on its way
+ * out) and *queued (optional) receive the counts after the round. */
 int mhd_server_tick(mhd_server_t* s, int* running, int* queued);
 
 /* Id of the oldest finished request not yet taken (-1 when none). */

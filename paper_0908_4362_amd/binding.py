@@ -79,6 +79,10 @@ def lib():
             "mhd_batch_set_graphs": ([vp, i], i),
             "mhd_batch_autotune": ([vp, i], i),
             "mhd_batch_tile": ([vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i)], i),
+            "mhd_batch_problem_layout": ([i, i, i, i, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                          ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], i),
+            "mhd_batch_add_inplace": ([vp, i, i, i, d, i, vp, vp, ctypes.POINTER(i)], i),
+            "mhd_batch_record": ([vp, vp], i),
             "mhd_server_now": ([], d),
             "mhd_server_create": ([ctypes.c_size_t, d, ctypes.POINTER(vp)], i),
             "mhd_server_destroy": ([vp], i),
@@ -247,6 +251,27 @@ def mhd_batch_add_device(b, nx: int, ny: int, nz: int, gamma: float, bc: int, de
     _check(lib().mhd_batch_add_device(b, nx, ny, nz, gamma, bc, ctypes.c_void_p(_dev_ptr(dev_state)),
                                       ctypes.byref(pid)))
     return pid.value
+
+
+def mhd_batch_problem_layout(nx: int, ny: int, nz: int, dtype: int):
+    """(offset of conserved fields copy 0, offset of face fields copy 0, offset of the control block, block bytes)."""
+    v = [ctypes.c_size_t() for _ in range(4)]
+    _check(lib().mhd_batch_problem_layout(nx, ny, nz, dtype, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def mhd_batch_add_inplace(b, nx: int, ny: int, nz: int, gamma: float, bc: int, dev_block, ready=None) -> int:
+    """dev_block: a device buffer (torch tensor or address) of mhd_batch_problem_bytes bytes holding the initial
+    state at the copy-0 offsets; ready: a hipEvent_t address (or None)."""
+    pid = ctypes.c_int()
+    _check(lib().mhd_batch_add_inplace(b, nx, ny, nz, gamma, bc, ctypes.c_void_p(_dev_ptr(dev_block)),
+                                       None if ready is None else ctypes.c_void_p(int(ready)), ctypes.byref(pid)))
+    return pid.value
+
+
+def mhd_batch_record(b, event):
+    """event: a hipEvent_t address (e.g. torch.cuda.Event().cuda_event)."""
+    _check(lib().mhd_batch_record(b, ctypes.c_void_p(int(event))))
 
 
 def mhd_batch_remove(b, pid: int):

@@ -8,6 +8,12 @@
 // rule followed by the 12 batched sweeps; after its first step it is captured
 // in a HIP graph per sweep order and replayed. Every step returns both state
 // copies to copy 0, so between steps copy 0 is the state and copy 1 scratch.
+//
+// Nothing on the stepping path waits for the device: job tables are uploaded
+// from a ring of pinned staging buffers, control blocks are initialised by a
+// kernel, and graphs or table buffers that queued work may still use are
+// released only once the stream has drained past them. Problems added in
+// place (caller-owned memory) are added and removed without any wait.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,7 +43,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Prob {
     Grid g;
     double gamma;
-    void* mem;       // one allocation: u[0], u[1], b[0], b[1], control block, reduction slots
+    bool owned;      // mem allocated (and freed) by the batch
+    void* mem;       // one block: u[0], u[1], b[0], b[1], control block, reduction slots
     size_t bytes;
     void* u[2];
     void* b[2];
@@ -64,6 +71,29 @@ struct Cohort {
 
 using ShapeKey = std::array<int, 4>;   // nx, ny, nz, kind
 
+// Pinned host staging for table uploads: a slot is rewritten only after the
+// copy that last read it has completed.
+struct Staging {
+    void* host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+constexpr int kStaging = 4;
+
+__global__ void init_ctl_kernel(Ctl* c)
+{
+    if (threadIdx.x == 0) {
+        c->dt = 0.0;
+        c->t = 0.0;
+        c->t_stop = -1.0;
+        c->cmax = 0.0;
+        c->divb = 0.0;
+        c->status = 0;
+        c->pad = 0;
+    }
+}
+
 }  // namespace
 
 struct mhd_batch {
@@ -77,6 +107,10 @@ struct mhd_batch {
     std::map<int, Prob> probs;
     std::vector<Cohort> cohorts;
     std::map<ShapeKey, std::pair<int, int>> tuned;   // tile per grid shape and kind
+    Staging staging[kStaging];
+    int next_staging;
+    std::vector<hipGraphExec_t> dead_graphs;   // released once the stream has drained past them
+    std::vector<void*> dead_dev;
 };
 
 namespace {
@@ -153,26 +187,66 @@ bool grid_ok(int nx, int ny, int nz, double gamma, int bc)
            std::isfinite(gamma) && (bc == MHD_BC_PERIODIC || bc == MHD_BC_OUTFLOW);
 }
 
-void drop_graphs(Cohort& c)
+// Release retired graphs and buffers once no queued work can use them
+// (wait: drain the stream first).
+void reap(mhd_batch* b, bool wait)
+{
+    if (b->dead_graphs.empty() && b->dead_dev.empty()) return;
+    if (wait)
+        (void)hipStreamSynchronize(b->stream);
+    else if (hipStreamQuery(b->stream) != hipSuccess)
+        return;
+    for (hipGraphExec_t g : b->dead_graphs) (void)hipGraphExecDestroy(g);
+    for (void* p : b->dead_dev) (void)hipFree(p);
+    b->dead_graphs.clear();
+    b->dead_dev.clear();
+}
+
+void drop_graphs(mhd_batch* b, Cohort& c)
 {
     for (int q = 0; q < 3; q++) {
-        if (c.exec[q]) (void)hipGraphExecDestroy(c.exec[q]);
+        if (c.exec[q]) b->dead_graphs.push_back(c.exec[q]);
         c.exec[q] = nullptr;
     }
 }
 
-void free_cohort(Cohort& c)
+void free_cohort(mhd_batch* b, Cohort& c)
 {
-    drop_graphs(c);
-    if (c.dev) (void)hipFree(c.dev);
+    drop_graphs(b, c);
+    if (c.dev) b->dead_dev.push_back(c.dev);
     c.dev = nullptr;
     c.dev_bytes = 0;
+}
+
+// Stream-ordered upload of host data through the pinned staging ring.
+int upload(mhd_batch* b, void* dst, const void* src, size_t bytes)
+{
+    Staging& st = b->staging[b->next_staging];
+    b->next_staging = (b->next_staging + 1) % kStaging;
+    if (st.pending) {
+        HIPCHK(hipEventSynchronize(st.done), "staging wait");
+        st.pending = false;
+    }
+    if (st.bytes < bytes) {
+        if (st.host) (void)hipHostFree(st.host);
+        st.host = nullptr;
+        st.bytes = 0;
+        const size_t want = std::max(bytes, (size_t)1 << 16);
+        HIPCHK(hipHostMalloc(&st.host, want, hipHostMallocDefault), "pinned staging allocation");
+        st.bytes = want;
+    }
+    if (!st.done) HIPCHK(hipEventCreateWithFlags(&st.done, hipEventDisableTiming), "hipEventCreate");
+    std::memcpy(st.host, src, bytes);
+    HIPCHK(hipMemcpyAsync(dst, st.host, bytes, hipMemcpyHostToDevice, b->stream), "table upload");
+    HIPCHK(hipEventRecord(st.done, b->stream), "hipEventRecord");
+    st.pending = true;
+    return MHD_OK;
 }
 
 // Job table and per-kind tile tables of a cohort, rebuilt in device memory.
 int build_tables(mhd_batch* b, Cohort& c)
 {
-    drop_graphs(c);
+    drop_graphs(b, c);
     const int n = (int)c.ids.size();
     std::vector<BJob> jobs(n);
     std::vector<TileDesc> td[mhd::KIND_COUNT];
@@ -216,12 +290,9 @@ int build_tables(mhd_batch* b, Cohort& c)
     const size_t jb = align_up(n * sizeof(BJob)), tb = align_up((n + 1) * sizeof(TileDesc));
     const size_t need = jb + mhd::KIND_COUNT * tb;
     if (need > c.dev_bytes) {
-        if (c.dev) {
-            HIPCHK(hipStreamSynchronize(b->stream), "stream sync");
-            (void)hipFree(c.dev);
-            c.dev = nullptr;
-            c.dev_bytes = 0;
-        }
+        if (c.dev) b->dead_dev.push_back(c.dev);   // queued steps may still read the old tables
+        c.dev = nullptr;
+        c.dev_bytes = 0;
         hipError_t e = hipMalloc(&c.dev, need);
         if (e != hipSuccess) {
             c.dev = nullptr;
@@ -231,16 +302,16 @@ int build_tables(mhd_batch* b, Cohort& c)
         }
         c.dev_bytes = need;
     }
+    // one image of all tables, uploaded in stream order (queued steps that use
+    // the previous tables run before the copy)
+    std::vector<char> img(need, 0);
+    std::memcpy(img.data(), jobs.data(), n * sizeof(BJob));
+    for (int k = 0; k < mhd::KIND_COUNT; k++)
+        std::memcpy(img.data() + jb + k * tb, td[k].data(), (n + 1) * sizeof(TileDesc));
     char* base = static_cast<char*>(c.dev);
     c.jobs = reinterpret_cast<BJob*>(base);
-    HIPCHK(hipMemcpyAsync(c.jobs, jobs.data(), n * sizeof(BJob), hipMemcpyHostToDevice, b->stream), "job table");
-    for (int k = 0; k < mhd::KIND_COUNT; k++) {
-        c.td[k] = reinterpret_cast<TileDesc*>(base + jb + k * tb);
-        HIPCHK(hipMemcpyAsync(c.td[k], td[k].data(), (n + 1) * sizeof(TileDesc), hipMemcpyHostToDevice, b->stream),
-               "tile table");
-    }
-    // the host vectors are released on return: wait for the copies
-    HIPCHK(hipStreamSynchronize(b->stream), "stream sync");
+    for (int k = 0; k < mhd::KIND_COUNT; k++) c.td[k] = reinterpret_cast<TileDesc*>(base + jb + k * tb);
+    if (int rc = upload(b, c.dev, img.data(), need)) return rc;
     c.dirty = false;
     c.cmax_valid = false;
     return MHD_OK;
@@ -341,50 +412,27 @@ Cohort& cohort_for(mhd_batch* b, long long s)
     return b->cohorts.back();
 }
 
-int add_problem(mhd_batch* b, int nx, int ny, int nz, double gamma, int bc, const void* state, hipMemcpyKind kind,
-                int* id)
+// Place a problem's arrays in its block and initialise its control block on
+// the batch's stream.
+int place(mhd_batch* b, Prob& p, void* block)
 {
-    if (!b) return fail(MHD_ERR_ARG, "null batch");
-    if (!id) return fail(MHD_ERR_ARG, "null output pointer");
-    if (!state) return fail(MHD_ERR_ARG, "null state pointer");
-    if (!grid_ok(nx, ny, nz, gamma, bc)) return fail(MHD_ERR_ARG, "invalid grid, gamma or boundary condition");
-    if (int rc = set_current(b)) return rc;
-    Prob p;
-    p.g.n[0] = nx;
-    p.g.n[1] = ny;
-    p.g.n[2] = nz;
-    p.g.bc = bc;
-    p.g.N = (long long)nx * ny * nz;
-    p.gamma = gamma;
-    p.s = 0;
     size_t offs[6];
     p.bytes = problem_layout(p.g, b->dtype, offs);
-    p.mem = nullptr;
-    hipError_t e = hipMalloc(&p.mem, p.bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return e == hipErrorOutOfMemory ? fail(MHD_ERR_OOM, "device allocation failed") : hip_fail(e, "hipMalloc");
-    }
-    char* base = static_cast<char*>(p.mem);
+    p.mem = block;
+    char* base = static_cast<char*>(block);
     p.u[0] = base + offs[0];
     p.u[1] = base + offs[1];
     p.b[0] = base + offs[2];
     p.b[1] = base + offs[3];
     p.ctl = reinterpret_cast<Ctl*>(base + offs[4]);
     p.parts = reinterpret_cast<unsigned long long*>(base + offs[5]);
-    const size_t N = (size_t)p.g.N, es = b->esize;
-    const char* src = static_cast<const char*>(state);
-    Ctl c0;
-    std::memset(&c0, 0, sizeof(c0));
-    c0.t_stop = -1.0;
-    e = hipMemcpyAsync(p.u[0], src, 5 * N * es, kind, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(p.b[0], src + 5 * N * es, 3 * N * es, kind, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(p.ctl, &c0, sizeof(Ctl), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);   // c0 lives on this stack frame
-    if (e != hipSuccess) {
-        (void)hipFree(p.mem);
-        return hip_fail(e, "state copy in");
-    }
+    hipLaunchKernelGGL(init_ctl_kernel, dim3(1), dim3(64), 0, b->stream, p.ctl);
+    HIPCHK(hipGetLastError(), "control block init");
+    return MHD_OK;
+}
+
+int enlist(mhd_batch* b, const Prob& p, int* id)
+{
     const int nid = b->next_id++;
     b->probs[nid] = p;
     Cohort& c = cohort_for(b, 0);
@@ -392,6 +440,54 @@ int add_problem(mhd_batch* b, int nx, int ny, int nz, double gamma, int bc, cons
     c.dirty = true;
     *id = nid;
     return MHD_OK;
+}
+
+bool make_prob(Prob& p, int nx, int ny, int nz, double gamma, int bc)
+{
+    if (!grid_ok(nx, ny, nz, gamma, bc)) return false;
+    p.g.n[0] = nx;
+    p.g.n[1] = ny;
+    p.g.n[2] = nz;
+    p.g.bc = bc;
+    p.g.N = (long long)nx * ny * nz;
+    p.gamma = gamma;
+    p.s = 0;
+    return true;
+}
+
+int add_problem(mhd_batch* b, int nx, int ny, int nz, double gamma, int bc, const void* state, hipMemcpyKind kind,
+                int* id)
+{
+    if (!b) return fail(MHD_ERR_ARG, "null batch");
+    if (!id) return fail(MHD_ERR_ARG, "null output pointer");
+    if (!state) return fail(MHD_ERR_ARG, "null state pointer");
+    Prob p;
+    if (!make_prob(p, nx, ny, nz, gamma, bc)) return fail(MHD_ERR_ARG, "invalid grid, gamma or boundary condition");
+    if (int rc = set_current(b)) return rc;
+    size_t offs[6];
+    void* block = nullptr;
+    hipError_t e = hipMalloc(&block, problem_layout(p.g, b->dtype, offs));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? fail(MHD_ERR_OOM, "device allocation failed") : hip_fail(e, "hipMalloc");
+    }
+    p.owned = true;
+    int rc = place(b, p, block);
+    const size_t N = (size_t)p.g.N, es = b->esize;
+    const char* src = static_cast<const char*>(state);
+    if (rc == MHD_OK) {
+        e = hipMemcpyAsync(p.u[0], src, 5 * N * es, kind, b->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(p.b[0], src + 5 * N * es, 3 * N * es, kind, b->stream);
+        // the caller may reuse its buffer on return
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) rc = hip_fail(e, "state copy in");
+    }
+    if (rc != MHD_OK) {
+        (void)hipStreamSynchronize(b->stream);
+        (void)hipFree(block);
+        return rc;
+    }
+    return enlist(b, p, id);
 }
 
 Prob* find(mhd_batch* b, int id)
@@ -455,8 +551,8 @@ int autotune(mhd_batch* b, int reps)
         }
         if (rc) break;
     }
-    (void)hipStreamSynchronize(b->stream);
-    free_cohort(tmp);
+    free_cohort(b, tmp);
+    reap(b, true);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     for (auto& c : b->cohorts) c.dirty = true;
@@ -491,6 +587,7 @@ int mhd_batch_create(int dtype, mhd_batch_t** out)
     b->esize = dtype == MHD_F64 ? 8 : 4;
     b->graphs = true;
     b->next_id = 1;
+    b->next_staging = 0;
     b->own_stream = nullptr;
     hipError_t e = hipGetDevice(&b->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking);
@@ -507,9 +604,14 @@ int mhd_batch_destroy(mhd_batch_t* b)
 {
     if (!b) return MHD_OK;
     (void)set_current(b);
-    (void)hipStreamSynchronize(b->stream);
-    for (auto& c : b->cohorts) free_cohort(c);
-    for (auto& kv : b->probs) (void)hipFree(kv.second.mem);
+    for (auto& c : b->cohorts) free_cohort(b, c);
+    reap(b, true);
+    for (auto& kv : b->probs)
+        if (kv.second.owned) (void)hipFree(kv.second.mem);
+    for (auto& st : b->staging) {
+        if (st.host) (void)hipHostFree(st.host);
+        if (st.done) (void)hipEventDestroy(st.done);
+    }
     if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
     delete b;
     return MHD_OK;
@@ -534,24 +636,69 @@ int mhd_batch_add_device(mhd_batch_t* b, int nx, int ny, int nz, double gamma, i
     return add_problem(b, nx, ny, nz, gamma, bc, dev_state, hipMemcpyDeviceToDevice, id);
 }
 
+int mhd_batch_problem_layout(int nx, int ny, int nz, int dtype, size_t* off_u0, size_t* off_b0, size_t* off_ctl,
+                             size_t* bytes)
+{
+    if (!grid_ok(nx, ny, nz, 2.0, MHD_BC_PERIODIC) || (dtype != MHD_F32 && dtype != MHD_F64))
+        return fail(MHD_ERR_ARG, "invalid grid or dtype");
+    Grid g;
+    g.n[0] = nx;
+    g.n[1] = ny;
+    g.n[2] = nz;
+    g.bc = 0;
+    g.N = (long long)nx * ny * nz;
+    size_t offs[6];
+    const size_t total = problem_layout(g, dtype, offs);
+    if (off_u0) *off_u0 = offs[0];
+    if (off_b0) *off_b0 = offs[2];
+    if (off_ctl) *off_ctl = offs[4];
+    if (bytes) *bytes = total;
+    return MHD_OK;
+}
+
+int mhd_batch_add_inplace(mhd_batch_t* b, int nx, int ny, int nz, double gamma, int bc, void* dev_block, void* ready,
+                          int* id)
+{
+    if (!b) return fail(MHD_ERR_ARG, "null batch");
+    if (!id || !dev_block) return fail(MHD_ERR_ARG, "null pointer");
+    Prob p;
+    if (!make_prob(p, nx, ny, nz, gamma, bc)) return fail(MHD_ERR_ARG, "invalid grid, gamma or boundary condition");
+    if (int rc = set_current(b)) return rc;
+    if (ready) HIPCHK(hipStreamWaitEvent(b->stream, static_cast<hipEvent_t>(ready), 0), "hipStreamWaitEvent");
+    p.owned = false;
+    if (int rc = place(b, p, dev_block)) return rc;
+    return enlist(b, p, id);
+}
+
+int mhd_batch_record(mhd_batch_t* b, void* event)
+{
+    if (!b || !event) return fail(MHD_ERR_ARG, "null pointer");
+    if (int rc = set_current(b)) return rc;
+    HIPCHK(hipEventRecord(static_cast<hipEvent_t>(event), b->stream), "hipEventRecord");
+    return MHD_OK;
+}
+
 int mhd_batch_remove(mhd_batch_t* b, int id)
 {
     if (!b) return fail(MHD_ERR_ARG, "null batch");
     Prob* p = find(b, id);
     if (!p) return fail(MHD_ERR_ARG, "unknown problem id");
     if (int rc = set_current(b)) return rc;
-    HIPCHK(hipStreamSynchronize(b->stream), "stream sync");
     for (auto& c : b->cohorts) {
         auto it = std::find(c.ids.begin(), c.ids.end(), id);
         if (it != c.ids.end()) {
             c.ids.erase(it);
             c.dirty = true;
-            drop_graphs(c);
-            if (c.ids.empty()) free_cohort(c);
+            drop_graphs(b, c);
+            if (c.ids.empty()) free_cohort(b, c);
         }
     }
-    HIPCHK(hipFree(p->mem), "hipFree");
+    if (p->owned) {
+        HIPCHK(hipStreamSynchronize(b->stream), "stream sync");
+        HIPCHK(hipFree(p->mem), "hipFree");
+    }
     b->probs.erase(id);
+    reap(b, false);
     return MHD_OK;
 }
 
@@ -571,6 +718,7 @@ int mhd_batch_step(mhd_batch_t* b, int n, double cfl)
     if (n < 0) return fail(MHD_ERR_ARG, "negative step count");
     if (!(cfl > 0.0 && cfl <= 1.0)) return fail(MHD_ERR_ARG, "cfl must be in (0, 1]");
     if (int rc = set_current(b)) return rc;
+    reap(b, false);
     for (int k = 0; k < n; k++)
         for (auto& c : b->cohorts) {
             if (c.ids.empty()) continue;
