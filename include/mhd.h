@@ -63,9 +63,12 @@ int mhd_destroy(mhd_t* h);
  * null stream) for all later work of this handle. */
 int mhd_set_stream(mhd_t* h, void* stream);
 
-/* Copy a state in (layout above) from host memory (synchronous) or from device
- * memory (asynchronous on the handle's stream); resets t = 0 and the step
- * counter s = 0. The caller keeps ownership of the buffer. */
+/* Copy a state in (layout above) from host memory or from device memory;
+ * resets t = 0 and the step counter s = 0, then checks it on the device and
+ * returns MHD_ERR_ARG if a value is not finite or a density is not positive
+ * (the handle then refuses to step, with MHD_ERR_ARG, until a valid state is
+ * set). Both variants return when the copy and the check are done. The
+ * caller keeps ownership of the buffer. */
 int mhd_set_state(mhd_t* h, const void* host_state);
 int mhd_set_state_device(mhd_t* h, const void* dev_state);
 
@@ -84,7 +87,8 @@ int mhd_get_state_device(mhd_t* h, void* dev_state);
  * dt is clipped so that t lands on it, and later steps do nothing.
  * Returns MHD_ERR_NONFINITE if some step met a NaN/inf/non-positive c_max;
  * the state is then the one that step started from, and stays frozen until
- * mhd_set_state. */
+ * mhd_set_state. Returns MHD_ERR_ARG (nothing advances) while the state set
+ * last is one mhd_set_state rejected. */
 int mhd_step(mhd_t* h, int n, double cfl);
 
 /* max over cells of |sum_d (B_d(c + e_d) - B_d(c))| in unit cells; with
@@ -145,6 +149,19 @@ int mhd_timing_read(mhd_t* h, int kind, double* total_ms, int64_t* launches);
 
 /* Number of device bytes a handle of this size holds. */
 size_t mhd_state_bytes(int nx, int ny, int nz, int dtype);
+
+/* Size of a caller-owned workspace that can hold all of a handle's device
+ * memory (two state copies, control block, reduction slots); 0 for invalid
+ * arguments. */
+size_t mhd_workspace_bytes(int nx, int ny, int nz, int dtype);
+
+/* Move the handle into a caller-owned device buffer (e.g. memory a PyTorch
+ * allocator owns) of at least mhd_workspace_bytes bytes, 256-byte aligned:
+ * the handle releases its own allocations and never frees the workspace,
+ * which must outlive the handle. The state is then undefined, t = 0 and
+ * s = 0 (call mhd_set_state); MHD_ERR_ARG for a null, misaligned or too
+ * small buffer (the handle is then unchanged). Synchronises the stream. */
+int mhd_bind_workspace(mhd_t* h, void* dev, size_t bytes);
 
 /* Headless diagnostics: the derived fields one would render (the paper shows
  * density, gas pressure and field images, Sec. 4.4 and Sec. 5), computed on

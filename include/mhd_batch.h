@@ -60,7 +60,8 @@ size_t mhd_batch_problem_bytes(int nx, int ny, int nz, int dtype);
  * (copied asynchronously on the batch's stream), layout as in mhd.h. The new
  * problem starts at t = 0, s = 0, no stop time; *id receives its handle
  * (ids are never reused within a batch). MHD_ERR_OOM when its allocation
- * fails; the batch is then unchanged. */
+ * fails, MHD_ERR_ARG when the state has a non-finite value or a non-positive
+ * density (checked on the device); the batch is then unchanged. */
 int mhd_batch_add(mhd_batch_t* b, int nx, int ny, int nz, double gamma, int bc, const void* host_state, int* id);
 int mhd_batch_add_device(mhd_batch_t* b, int nx, int ny, int nz, double gamma, int bc, const void* dev_state,
                          int* id);
@@ -78,7 +79,9 @@ int mhd_batch_problem_layout(int nx, int ny, int nz, int dtype, size_t* off_u0, 
  * which they do, and the batch's stream waits for it. Nothing is copied and
  * the host does not wait. The caller keeps the block: after
  * mhd_batch_remove it may reuse it once the batch's stream has passed the
- * removal (mhd_batch_record an event and wait for it). */
+ * removal (mhd_batch_record an event and wait for it). The state is checked
+ * on the device without waiting: a rejected one latches MHD_ERR_ARG in the
+ * problem's status and is never advanced. */
 int mhd_batch_add_inplace(mhd_batch_t* b, int nx, int ny, int nz, double gamma, int bc, void* dev_block, void* ready,
                           int* id);
 
@@ -112,8 +115,9 @@ int mhd_batch_get_time(mhd_batch_t* b, int id, double* t, int64_t* s);
 /* Stop time of one problem, as mhd_set_stop_time (negative: none). */
 int mhd_batch_set_stop_time(mhd_batch_t* b, int id, double t_stop);
 
-/* Status of one problem: MHD_OK, or MHD_ERR_NONFINITE once its c_max was
- * NaN, infinite or not positive (synchronises). */
+/* Status of one problem: MHD_OK, MHD_ERR_NONFINITE once its c_max was NaN,
+ * infinite or not positive, or MHD_ERR_ARG for a rejected initial state
+ * (synchronises). */
 int mhd_batch_status(mhd_batch_t* b, int id);
 
 /* Capture each cohort's full step in a HIP graph and replay it (enable = 1,

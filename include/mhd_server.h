@@ -66,7 +66,9 @@ int mhd_server_tick(mhd_server_t* s, int* running, int* queued);
 int mhd_server_poll(mhd_server_t* s, int* req);
 
 /* State of a request (MHD_REQ_*), its simulation time and steps taken, its
- * solver status (MHD_OK or MHD_ERR_NONFINITE), and its submission, admission
+ * solver status (MHD_OK, MHD_ERR_NONFINITE, MHD_ERR_ARG for an initial state
+ * with a non-finite value or a non-positive density, or MHD_ERR_OOM when it
+ * could never be placed), and its submission, admission
  * and finish times (negative while not reached). Any pointer may be null. */
 int mhd_server_info(mhd_server_t* s, int req, int* state, double* t_sim, int64_t* steps, int* status,
                     double* t_submit, double* t_admit, double* t_finish);

@@ -59,6 +59,8 @@ def lib():
             "mhd_cmax": ([vp, ctypes.POINTER(d)], i),
             "mhd_step_dt": ([vp, d, ctypes.c_int64], i),
             "mhd_state_bytes": ([i, i, i, i], ctypes.c_size_t),
+            "mhd_workspace_bytes": ([i, i, i, i], ctypes.c_size_t),
+            "mhd_bind_workspace": ([vp, vp, ctypes.c_size_t], i),
             "mhd_timing": ([vp, i], i),
             "mhd_timing_read": ([vp, i, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64)], i),
             "mhd_diagnostic": ([vp, i, i, i, vp], i),
@@ -202,6 +204,15 @@ def mhd_step_dt(h, dt: float, s_order: int):
 
 def mhd_state_bytes(nx: int, ny: int, nz: int, dtype: int) -> int:
     return int(lib().mhd_state_bytes(nx, ny, nz, dtype))
+
+
+def mhd_workspace_bytes(nx: int, ny: int, nz: int, dtype: int) -> int:
+    return int(lib().mhd_workspace_bytes(nx, ny, nz, dtype))
+
+
+def mhd_bind_workspace(h, dev, nbytes: int):
+    """dev: a device buffer (torch tensor or address) the caller keeps alive longer than the handle."""
+    _check(lib().mhd_bind_workspace(h, ctypes.c_void_p(_dev_ptr(dev)), int(nbytes)))
 
 
 def mhd_timing(h, enable: bool):

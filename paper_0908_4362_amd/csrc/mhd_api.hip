@@ -38,6 +38,7 @@ struct mhd_solver {
     long long s;          // step counter (host mirror; the sweep order needs it on the host)
     int device;
     bool cmax_valid;      // parts hold the CFL maxima of the current state (from the last step)
+    bool bound;           // buffers live in a caller-owned workspace (mhd_bind_workspace)
     // optional per-kernel timing with HIP events on the handle's stream
     bool timing;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[MHD_K_COUNT];
@@ -216,18 +217,35 @@ extern "C" {
 
 const char* mhd_last_error(void) { return g_err.c_str(); }
 
-size_t mhd_state_bytes(int nx, int ny, int nz, int dtype)
+// Byte offsets of a handle's six buffers (conserved fields x2, face fields
+// x2, control block, reduction slots) inside one workspace, 256-aligned.
+static size_t workspace_layout(const Grid& g, size_t es, size_t offs[6])
+{
+    const size_t N = (size_t)g.N;
+    const size_t sizes[6] = {5 * N * es, 5 * N * es, 3 * N * es, 3 * N * es, sizeof(Ctl),
+                             2 * mhd::reduce_capacity(g) * sizeof(unsigned long long)};
+    size_t off = 0;
+    for (int k = 0; k < 6; k++) {
+        offs[k] = off;
+        off += (sizes[k] + 255) / 256 * 256;
+    }
+    return off;
+}
+
+size_t mhd_workspace_bytes(int nx, int ny, int nz, int dtype)
 {
     if (nx < 1 || ny < 1 || nz < 1 || (dtype != MHD_F32 && dtype != MHD_F64)) return 0;
-    const size_t es = dtype == MHD_F64 ? 8 : 4;
     mhd::Grid g;
     g.n[0] = nx;
     g.n[1] = ny;
     g.n[2] = nz;
     g.bc = 0;
     g.N = (long long)nx * ny * nz;
-    return 2 * 8 * (size_t)g.N * es + sizeof(Ctl) + 2 * mhd::reduce_capacity(g) * sizeof(unsigned long long);
+    size_t offs[6];
+    return workspace_layout(g, dtype == MHD_F64 ? 8 : 4, offs);
 }
+
+size_t mhd_state_bytes(int nx, int ny, int nz, int dtype) { return mhd_workspace_bytes(nx, ny, nz, dtype); }
 
 int mhd_create(int nx, int ny, int nz, double gamma, int bc, int dtype, mhd_t** out)
 {
@@ -252,6 +270,7 @@ int mhd_create(int nx, int ny, int nz, double gamma, int bc, int dtype, mhd_t** 
     h->stream = nullptr;
     h->s = 0;
     h->cmax_valid = false;
+    h->bound = false;
     h->timing = false;
     for (int k = 0; k < MHD_K_COUNT; k++) {
         h->total_ms[k] = 0.0;
@@ -303,12 +322,14 @@ int mhd_destroy(mhd_t* h)
     if (!h) return MHD_OK;
     (void)set_current(h);
     (void)hipStreamSynchronize(h->stream);
-    (void)hipFree(h->u[0]);
-    (void)hipFree(h->u[1]);
-    (void)hipFree(h->b[0]);
-    (void)hipFree(h->b[1]);
-    (void)hipFree(h->ctl);
-    (void)hipFree(h->parts);
+    if (!h->bound) {
+        (void)hipFree(h->u[0]);
+        (void)hipFree(h->u[1]);
+        (void)hipFree(h->b[0]);
+        (void)hipFree(h->b[1]);
+        (void)hipFree(h->ctl);
+        (void)hipFree(h->parts);
+    }
     for (int k = 0; k < MHD_K_COUNT; k++)
         for (auto& pr : h->pending[k]) {
             (void)hipEventDestroy(pr.first);
@@ -316,6 +337,42 @@ int mhd_destroy(mhd_t* h)
         }
     for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
     delete h;
+    return MHD_OK;
+}
+
+int mhd_bind_workspace(mhd_t* h, void* dev, size_t bytes)
+{
+    if (int rc = check(h)) return rc;
+    if (!dev) return fail(MHD_ERR_ARG, "null workspace");
+    if (reinterpret_cast<uintptr_t>(dev) % 256 != 0) return fail(MHD_ERR_ARG, "workspace must be 256-byte aligned");
+    size_t offs[6];
+    const size_t need = workspace_layout(h->g, h->esize, offs);
+    if (bytes < need) return fail(MHD_ERR_ARG, "workspace smaller than mhd_workspace_bytes");
+    if (int rc = set_current(h)) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
+    char* base = static_cast<char*>(dev);
+    Ctl c0;
+    std::memset(&c0, 0, sizeof(c0));
+    c0.t_stop = -1.0;
+    HIPCHK(hipMemcpy(base + offs[4], &c0, sizeof(Ctl), hipMemcpyHostToDevice), "init control block");
+    if (!h->bound) {
+        (void)hipFree(h->u[0]);
+        (void)hipFree(h->u[1]);
+        (void)hipFree(h->b[0]);
+        (void)hipFree(h->b[1]);
+        (void)hipFree(h->ctl);
+        (void)hipFree(h->parts);
+    }
+    h->u[0] = base + offs[0];
+    h->u[1] = base + offs[1];
+    h->b[0] = base + offs[2];
+    h->b[1] = base + offs[3];
+    h->ctl = reinterpret_cast<Ctl*>(base + offs[4]);
+    h->parts = reinterpret_cast<unsigned long long*>(base + offs[5]);
+    h->ucur = h->bcur = 0;
+    h->s = 0;
+    h->cmax_valid = false;
+    h->bound = true;
     return MHD_OK;
 }
 
@@ -359,13 +416,32 @@ static int copy_out(mhd_t* h, void* dst, hipMemcpyKind kind)
     return MHD_OK;
 }
 
+// Check the state just copied in (after reset_time cleared the status): a
+// non-finite value or a non-positive density is rejected.
+static int validate(mhd_t* h)
+{
+    const long long N = h->g.N;
+    hipError_t e = h->dtype == MHD_F64
+                       ? mhd::launch_validate<double>(static_cast<const double*>(h->u[0]),
+                                                      static_cast<const double*>(h->b[0]), N, h->ctl, h->stream)
+                       : mhd::launch_validate<float>(static_cast<const float*>(h->u[0]),
+                                                     static_cast<const float*>(h->b[0]), N, h->ctl, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "state check launch");
+    int status = 0;
+    HIPCHK(hipMemcpyAsync(&status, &h->ctl->status, sizeof(int), hipMemcpyDeviceToHost, h->stream), "read status");
+    HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
+    if (status != 0) return fail(MHD_ERR_ARG, "state has a non-finite value or a non-positive density");
+    return MHD_OK;
+}
+
 int mhd_set_state(mhd_t* h, const void* host_state)
 {
     if (int rc = check(h)) return rc;
     if (!host_state) return fail(MHD_ERR_ARG, "null state pointer");
     if (int rc = set_current(h)) return rc;
     if (int rc = copy_in(h, host_state, hipMemcpyHostToDevice)) return rc;
-    return reset_time(h);
+    if (int rc = reset_time(h)) return rc;
+    return validate(h);
 }
 
 int mhd_set_state_device(mhd_t* h, const void* dev_state)
@@ -374,7 +450,8 @@ int mhd_set_state_device(mhd_t* h, const void* dev_state)
     if (!dev_state) return fail(MHD_ERR_ARG, "null state pointer");
     if (int rc = set_current(h)) return rc;
     if (int rc = copy_in(h, dev_state, hipMemcpyDeviceToDevice)) return rc;
-    return reset_time(h);
+    if (int rc = reset_time(h)) return rc;
+    return validate(h);
 }
 
 int mhd_get_state(mhd_t* h, void* host_state)
@@ -406,6 +483,7 @@ int mhd_step(mhd_t* h, int n, double cfl)
     int status = 0;
     HIPCHK(hipMemcpyAsync(&status, &h->ctl->status, sizeof(int), hipMemcpyDeviceToHost, h->stream), "read status");
     HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
+    if (status == -1) return fail(MHD_ERR_ARG, "the state set last was rejected; set a valid state");
     if (status != 0) return fail(MHD_ERR_NONFINITE, "non-finite or non-positive c_max; state frozen");
     return MHD_OK;
 }

@@ -431,6 +431,19 @@ int place(mhd_batch* b, Prob& p, void* block)
     return MHD_OK;
 }
 
+// Device check of a problem's copy-0 state (after place()): a non-finite
+// value or a non-positive density latches status -1.
+int check_state(mhd_batch* b, const Prob& p)
+{
+    hipError_t e = b->dtype == MHD_F64
+                       ? mhd::launch_validate<double>(static_cast<const double*>(p.u[0]),
+                                                      static_cast<const double*>(p.b[0]), p.g.N, p.ctl, b->stream)
+                       : mhd::launch_validate<float>(static_cast<const float*>(p.u[0]),
+                                                     static_cast<const float*>(p.b[0]), p.g.N, p.ctl, b->stream);
+    HIPCHK(e, "state check launch");
+    return MHD_OK;
+}
+
 int enlist(mhd_batch* b, const Prob& p, int* id)
 {
     const int nid = b->next_id++;
@@ -478,9 +491,18 @@ int add_problem(mhd_batch* b, int nx, int ny, int nz, double gamma, int bc, cons
     if (rc == MHD_OK) {
         e = hipMemcpyAsync(p.u[0], src, 5 * N * es, kind, b->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(p.b[0], src + 5 * N * es, 3 * N * es, kind, b->stream);
-        // the caller may reuse its buffer on return
-        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
         if (e != hipSuccess) rc = hip_fail(e, "state copy in");
+    }
+    if (rc == MHD_OK) rc = check_state(b, p);
+    if (rc == MHD_OK) {
+        // the caller may reuse its buffer on return; a rejected state is not added
+        int status = 0;
+        e = hipMemcpyAsync(&status, &p.ctl->status, sizeof(int), hipMemcpyDeviceToHost, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess)
+            rc = hip_fail(e, "state check");
+        else if (status != 0)
+            rc = fail(MHD_ERR_ARG, "state has a non-finite value or a non-positive density");
     }
     if (rc != MHD_OK) {
         (void)hipStreamSynchronize(b->stream);
@@ -667,6 +689,7 @@ int mhd_batch_add_inplace(mhd_batch_t* b, int nx, int ny, int nz, double gamma, 
     if (ready) HIPCHK(hipStreamWaitEvent(b->stream, static_cast<hipEvent_t>(ready), 0), "hipStreamWaitEvent");
     p.owned = false;
     if (int rc = place(b, p, dev_block)) return rc;
+    if (int rc = check_state(b, p)) return rc;   // a rejected state latches its status
     return enlist(b, p, id);
 }
 
@@ -788,6 +811,7 @@ int mhd_batch_status(mhd_batch_t* b, int id)
     if (int rc = set_current(b)) return rc;
     Ctl c;
     if (int rc = read_ctl(b, *p, &c)) return rc;
+    if (c.status == -1) return fail(MHD_ERR_ARG, "the problem's initial state was rejected");
     return c.status != 0 ? fail(MHD_ERR_NONFINITE, "non-finite or non-positive c_max; state frozen") : MHD_OK;
 }
 

@@ -1,7 +1,8 @@
 // Derived fields of a state for headless diagnostics, in place of the paper's
 // on-screen rendering of the density, pressure and field (Sec. 4.4): gas
 // pressure, magnetic pressure, speed, CFL speed and the cell divergence of B,
-// for the whole grid or for one plane of it.
+// for the whole grid or for one plane of it; and the check of an input state
+// (every value finite, density positive).
 #pragma once
 #include "mhd_kernels_impl.h"
 
@@ -63,7 +64,33 @@ __global__ void __launch_bounds__(256) diag_kernel(const T* __restrict__ u, cons
     }
 }
 
+// Input check: a non-finite value in any field or a non-positive density
+// latches status -1 in the control block (every offending thread stores the
+// same value; the status was cleared before the launch).
+template <typename T>
+__global__ void __launch_bounds__(256) validate_kernel(const T* __restrict__ u, const T* __restrict__ b, long long N,
+                                                       Ctl* __restrict__ ctl)
+{
+    bool bad = false;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
+        const T rho = u[c];
+        bad |= !(rho > T(0)) || !isfinite(rho);
+        for (int q = 1; q < 5; q++) bad |= !isfinite(u[q * N + c]);
+        for (int q = 0; q < 3; q++) bad |= !isfinite(b[q * N + c]);
+    }
+    if (bad) ctl->status = -1;
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_validate(const T* u, const T* b, long long N, Ctl* ctl, hipStream_t s)
+{
+    long long nb = (N + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL((validate_kernel<T>), dim3((unsigned)nb), dim3(256), 0, s, u, b, N, ctl);
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_diag(const T* u, const T* b, Grid g, double gamma, int kind, int axis, int index, T* out,

@@ -23,7 +23,7 @@ struct Ctl {
     double t_stop;  // < 0: none
     double cmax;    // c_max of the current state (from the last reduction)
     double divb;    // result of the last div B reduction
-    int status;     // 0 ok, -4 non-finite c_max (latched)
+    int status;     // 0 ok, -4 non-finite c_max, -1 invalid input state (latched)
     int pad;
 };
 
@@ -114,5 +114,10 @@ hipError_t launch_finish_batch(const BJob* jobs, const TileDesc* td, int njobs, 
 template <typename T>
 hipError_t launch_diag(const T* u, const T* b, Grid g, double gamma, int kind, int axis, int index, T* out,
                        hipStream_t s);
+
+// Input check of a state (u: 5 N, b: 3 N elements): sets ctl->status = -1 if
+// any value is not finite or some density is not positive.
+template <typename T>
+hipError_t launch_validate(const T* u, const T* b, long long N, Ctl* ctl, hipStream_t s);
 
 }  // namespace mhd

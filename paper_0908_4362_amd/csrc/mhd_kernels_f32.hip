@@ -17,4 +17,5 @@ template size_t tile_lds<float>(int, int, int);
 template hipError_t launch_batch<float>(int, bool, const BJob*, const TileDesc*, int, unsigned, size_t, int, int,
                                          hipStream_t);
 template hipError_t launch_diag<float>(const float*, const float*, Grid, double, int, int, int, float*, hipStream_t);
+template hipError_t launch_validate<float>(const float*, const float*, long long, Ctl*, hipStream_t);
 }  // namespace mhd

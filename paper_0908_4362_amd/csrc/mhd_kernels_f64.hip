@@ -89,4 +89,5 @@ template size_t tile_lds<double>(int, int, int);
 template hipError_t launch_batch<double>(int, bool, const BJob*, const TileDesc*, int, unsigned, size_t, int, int,
                                          hipStream_t);
 template hipError_t launch_diag<double>(const double*, const double*, Grid, double, int, int, int, double*, hipStream_t);
+template hipError_t launch_validate<double>(const double*, const double*, long long, Ctl*, hipStream_t);
 }  // namespace mhd

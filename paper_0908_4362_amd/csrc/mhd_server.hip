@@ -263,7 +263,7 @@ void finish(mhd_server* s, int id)
     mhd::Ctl c;
     std::memcpy(&c, static_cast<const char*>(r.host) + r.sbytes, sizeof(c));
     r.t_sim = c.t;
-    r.status = c.status != 0 ? MHD_ERR_NONFINITE : MHD_OK;
+    r.status = c.status == -1 ? MHD_ERR_ARG : (c.status != 0 ? MHD_ERR_NONFINITE : MHD_OK);
     s->free_blocks.emplace(r.bytes, r.block);
     r.block = nullptr;
     s->used -= r.bytes;

@@ -100,3 +100,14 @@ def test_batch_argument_errors_are_reported_before_device_use(libmhd):
         for dt, es in ((B.MHD_F32, 4), (B.MHD_F64, 8)):
             nbytes = B.mhd_batch_problem_bytes(nx, ny, nz, dt)
             assert 16 * nx * ny * nz * es < nbytes < 16 * nx * ny * nz * es + 6 * 256 + 8 * 65536
+
+
+def test_workspace_bytes(libmhd):
+    B = libmhd
+    assert B.mhd_workspace_bytes(0, 4, 4, B.MHD_F64) == 0
+    assert B.mhd_workspace_bytes(4, 4, 4, 9) == 0
+    for (nx, ny, nz) in ((32, 32, 32), (50, 7, 3), (256, 1, 1)):
+        for dt, es in ((B.MHD_F32, 4), (B.MHD_F64, 8)):
+            nb = B.mhd_workspace_bytes(nx, ny, nz, dt)
+            assert nb % 256 == 0 and nb >= 16 * nx * ny * nz * es
+            assert B.mhd_state_bytes(nx, ny, nz, dt) == nb

@@ -74,31 +74,47 @@ def test_stop_time_lands_exactly_and_then_no_op(B):
         assert sv.time()[0] > 5.5
 
 
-def test_nonfinite_state_is_reported_and_frozen(B):
+def test_invalid_state_is_rejected(B):
     s = P.random_smooth(20, 18, 16, seed=P.MASTER_SEED + 42)
-    s[0, 3, 4, 5] = np.nan
-    note("nan guard")
+    note("state check")
     with B.Solver(20, 18, 16, H.GAMMA53, 0, B.MHD_F64) as sv:
-        sv.set_state(s)
-        with pytest.raises(B.MHDError) as ei:
-            sv.step(2)
-        assert ei.value.code == B.MHD_ERR_NONFINITE
-        got = sv.get_state()
-        assert np.array_equal(got, s, equal_nan=True)
-        # still latched
-        with pytest.raises(B.MHDError):
-            sv.step(1)
-        # a fresh state clears it
-        s[0, 3, 4, 5] = 1.0
-        sv.set_state(s)
+        for field, value in ((0, np.nan), (0, 0.0), (0, -1.0), (4, np.inf), (6, np.nan)):
+            bad = s.copy()
+            bad[field, 3, 4, 5] = value
+            with pytest.raises(B.MHDError) as ei:
+                sv.set_state(bad)
+            assert ei.value.code == B.MHD_ERR_ARG
+            # the handle refuses to step a rejected state
+            with pytest.raises(B.MHDError) as ei:
+                sv.step(1)
+            assert ei.value.code == B.MHD_ERR_ARG
+        sv.set_state(s)          # a valid state clears it
         sv.step(1)
-    neg = P.random_smooth(20, 18, 16, seed=P.MASTER_SEED + 42)
-    neg[0] = -neg[0]
     with B.Solver(20, 18, 16, H.GAMMA53, 0, B.MHD_F32) as sv:
-        sv.set_state(neg)
+        bad = s.copy()
+        bad[0] = -bad[0]
         with pytest.raises(B.MHDError) as ei:
+            sv.set_state(bad)
+        assert ei.value.code == B.MHD_ERR_ARG
+
+
+def test_zero_cmax_is_reported_and_frozen(B):
+    """A valid state whose every wave speed is zero (v = 0, p = 0, B = 0):
+    the dt rule has no positive c_max; the step reports it and the state
+    stays as it was, latched until a new state is set."""
+    z = P.uniform(12, 10, 8, rho=1.0, p=0.0)
+    note("zero c_max")
+    for dtype in (B.MHD_F64, B.MHD_F32):
+        with B.Solver(12, 10, 8, H.GAMMA53, 0, dtype) as sv:
+            sv.set_state(z)
+            with pytest.raises(B.MHDError) as ei:
+                sv.step(2)
+            assert ei.value.code == B.MHD_ERR_NONFINITE
+            assert np.array_equal(sv.get_state(), z.astype(sv.np_dtype))
+            with pytest.raises(B.MHDError):
+                sv.step(1)
+            sv.set_state(P.random_smooth(12, 10, 8, seed=P.MASTER_SEED + 46))
             sv.step(1)
-        assert ei.value.code == B.MHD_ERR_NONFINITE
 
 
 def test_argument_errors(B):
@@ -180,3 +196,32 @@ def test_timing_counts_launches(B):
     # launches of each directional sub-operation
     assert counts == [4, 6, 6, 6, 6, 6, 6]
     assert all(m > 0 for m in ms)
+
+
+def test_bound_workspace_equals_owned_memory(B):
+    import torch
+
+    nx, ny, nz = 30, 22, 18
+    s = P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 47)
+    note("bound workspace")
+    for dtype in (B.MHD_F64, B.MHD_F32):
+        nb = B.mhd_workspace_bytes(nx, ny, nz, dtype)
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+        base = (ws.data_ptr() + 255) // 256 * 256
+        with B.Solver(nx, ny, nz, H.GAMMA53, 1, dtype) as sv:
+            with pytest.raises(B.MHDError) as ei:
+                B.mhd_bind_workspace(sv.h, base, nb - 1)
+            assert ei.value.code == B.MHD_ERR_ARG
+            with pytest.raises(B.MHDError):
+                B.mhd_bind_workspace(sv.h, base + 8, nb)
+            B.mhd_bind_workspace(sv.h, base, nb)
+            sv.set_state(s)
+            sv.step(3)
+            got = sv.get_state()
+            assert sv.time()[1] == 3
+        with B.Solver(nx, ny, nz, H.GAMMA53, 1, dtype) as ref:
+            ref.set_state(s)
+            ref.step(3)
+            assert np.array_equal(got, ref.get_state())
+        ws.zero_()           # still the caller's memory after the handle is gone
+        torch.cuda.synchronize()

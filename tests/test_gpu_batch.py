@@ -164,13 +164,18 @@ def test_batch_failure_is_isolated(B):
     good = P.random_smooth(22, 19, 13, seed=seed)
     bad = P.random_smooth(18, 18, 18, seed=seed + 1)
     bad[0, 3, 4, 5] = np.nan
+    stall = P.uniform(14, 12, 10, rho=1.0, p=0.0)   # valid, but no positive wave speed
     note("failure isolation")
     with B.Batch(B.MHD_F64) as bt:
         ig = bt.add(good, H.GAMMA53, 0)
-        ib = bt.add(bad, H.GAMMA53, 0)
+        with pytest.raises(B.MHDError) as ei:
+            bt.add(bad, H.GAMMA53, 0)
+        assert ei.value.code == B.MHD_ERR_ARG
+        assert B.mhd_batch_count(bt.b)[0] == 1
+        iz = bt.add(stall, H.GAMMA53, 0)
         bt.step(3)
-        assert bt.status(ib) == B.MHD_ERR_NONFINITE
-        assert np.array_equal(bt.get_state(ib), bad, equal_nan=True)
+        assert bt.status(iz) == B.MHD_ERR_NONFINITE
+        assert np.array_equal(bt.get_state(iz), stall)
         assert bt.status(ig) == B.MHD_OK
         assert np.array_equal(bt.get_state(ig), plain(B, good, H.GAMMA53, 0, 1, 3)[0])
 

@@ -103,17 +103,23 @@ def test_oversized_request_is_rejected(B):
 def test_failed_request_does_not_disturb_the_others(B):
     good = P.random_smooth(20, 16, 12, seed=P.MASTER_SEED + 610)
     bad = P.random_smooth(14, 14, 14, seed=P.MASTER_SEED + 611)
-    bad[0, 2, 3, 4] = np.nan           # c_max turns NaN
+    bad[0, 2, 3, 4] = np.nan           # rejected by the state check
+    stall = P.uniform(10, 12, 14, rho=1.0, p=0.0)   # no positive wave speed: c_max is 0
     note("serving failure isolation")
     with B.Server(1 << 30) as srv:
         rg = srv.submit(good, 5.0 / 3.0, 0, B.MHD_F64, 6)
         rb = srv.submit(bad, 5.0 / 3.0, 0, B.MHD_F64, 6)
+        rz = srv.submit(stall, 5.0 / 3.0, 0, B.MHD_F32, 6)
         done = {}
-        for _ in range(20):
+        for _ in range(40):
             srv.tick()
             for rid in srv.finished():
                 done[rid] = (srv.info(rid), srv.take(rid))
-        assert set(done) == {rg, rb}
-        assert done[rb][0]["status"] == B.MHD_ERR_NONFINITE
+            if len(done) == 3:
+                break
+        assert set(done) == {rg, rb, rz}
+        assert done[rb][0]["status"] == B.MHD_ERR_ARG
+        assert done[rz][0]["status"] == B.MHD_ERR_NONFINITE
+        assert np.array_equal(done[rz][1], stall.astype(np.float32))
         assert done[rg][0]["status"] == B.MHD_OK
         assert np.array_equal(done[rg][1], alone(B, good, 5.0 / 3.0, 0, B.MHD_F64, 6)[0])
