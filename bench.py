@@ -355,6 +355,47 @@ def run_serving(B, P, count, fracs, budget, steps):
     }
 
 
+# The paper's own timing workloads and its GTX 480 ms per full step (FP32, FP64): context for the
+# same workloads run here, not a target (other hardware).
+PAPER_CONFIGS = [
+    ("Brio-Wu 1D, 4096 cells, outflow", "brio_wu", 4096, (4.31, 5.95)),
+    ("Orszag-Tang 2D, 512^2, periodic", "orszag_tang", 512, (43.94, 56.26)),
+    ("Orszag-Tang 2D, 1024^2, periodic", "orszag_tang", 1024, (96.43, 144.48)),
+    ("3D blast, 128^3, periodic, B = (1,1,1)/sqrt3", "blast3", 128, (161.33, 276.40)),
+]
+
+
+def run_paper_configs(B, P, steps=20, warmup=3):
+    import torch
+
+    out = []
+    stream = torch.cuda.Stream()   # a stream of its own: steps replay from graphs
+    for name, kind, n, paper_ms in PAPER_CONFIGS:
+        if kind == "brio_wu":
+            s, gamma, bc = P.brio_wu(n), 2.0, B.MHD_BC_OUTFLOW
+        elif kind == "orszag_tang":
+            s, gamma, bc = P.orszag_tang(n), 5.0 / 3.0, B.MHD_BC_PERIODIC
+        else:
+            r = 1.0 / math.sqrt(3.0)
+            s, gamma, bc = P.blast(n, bvec=(r, r, r)), 5.0 / 3.0, B.MHD_BC_PERIODIC
+        nz, ny, nx = s.shape[1:]
+        row = {"workload": name}
+        for dtype, label, pms in ((B.MHD_F32, "fp32", paper_ms[0]), (B.MHD_F64, "fp64", paper_ms[1])):
+            with B.Solver(nx, ny, nz, gamma, bc, dtype) as sv:
+                B.mhd_set_stream(sv.h, stream)
+                sv.set_state(s)
+                sv.step(warmup, 0.7)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sv.step(steps, 0.7)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3 / steps
+            row[label] = {"ms_per_step": round(ms, 4), "cell_updates_per_s": round(nx * ny * nz / ms * 1e3, 1),
+                          "paper_gtx480_ms_per_step": pms, "speedup_vs_paper": round(pms / ms, 1)}
+        out.append(row)
+    return out
+
+
 def cpu_baseline(P, n, sample):
     """The oracle, single thread, on a bounded sample: one full step of a
     sample^3 box cut from the centre of the n^3 blast (outflow edges)."""
@@ -399,6 +440,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--batch-tune", type=int, default=3, help="autotuner launches per candidate (0: off)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--no-paper-configs", action="store_true", help="skip the paper's own timing workloads")
     ap.add_argument("--serve-count", type=int, default=96)
     ap.add_argument("--serve-rates", default="0.5,1.0", help="arrival rates as fractions of saturation")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
@@ -467,6 +509,9 @@ def main():
             "effective_step_bandwidth_GBs": round(STEP_WORDS * 4 * ncell * args.steps / sec32 / 1e9, 1),
             "kernels_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in kern32.items()},
         }
+    if not args.no_paper_configs:
+        print("bench: the paper's timing workloads", file=sys.stderr, flush=True)
+        out["paper_configs"] = run_paper_configs(B, P)
     if not args.no_batch:
         print("bench: batched workload", file=sys.stderr, flush=True)
         out["batched"] = run_batched(B, P, args.batch_count, args.batch_steps, 2, B.MHD_F32, args.batch_tune)

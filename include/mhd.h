@@ -63,6 +63,13 @@ int mhd_destroy(mhd_t* h);
  * null stream) for all later work of this handle. */
 int mhd_set_stream(mhd_t* h, void* stream);
 
+/* Replay full steps from HIP graphs (enable = 1, the default) or issue every
+ * launch directly (0). Replay applies on a stream other than the null
+ * stream, with per-kernel timing off: each sweep order's step (dt rule and
+ * 12 sweeps) is captured once and relaunched, which removes the per-launch
+ * host cost that dominates small grids. Results are identical either way. */
+int mhd_set_graphs(mhd_t* h, int enable);
+
 /* Copy a state in (layout above) from host memory or from device memory;
  * resets t = 0 and the step counter s = 0, then checks it on the device and
  * returns MHD_ERR_ARG if a value is not finite or a density is not positive

@@ -44,6 +44,7 @@ def lib():
             "mhd_create": ([i, i, i, d, i, i, ctypes.POINTER(vp)], i),
             "mhd_destroy": ([vp], i),
             "mhd_set_stream": ([vp, vp], i),
+            "mhd_set_graphs": ([vp, i], i),
             "mhd_set_state": ([vp, vp], i),
             "mhd_set_state_device": ([vp, vp], i),
             "mhd_get_state": ([vp, vp], i),
@@ -137,6 +138,10 @@ def mhd_set_stream(h, stream):
     """stream: a torch.cuda.Stream, a raw hipStream_t address, or None."""
     ptr = None if stream is None else (stream if isinstance(stream, int) else int(stream.cuda_stream))
     _check(lib().mhd_set_stream(h, ptr))
+
+
+def mhd_set_graphs(h, enable: bool):
+    _check(lib().mhd_set_graphs(h, 1 if enable else 0))
 
 
 def mhd_set_state(h, host_state: np.ndarray):

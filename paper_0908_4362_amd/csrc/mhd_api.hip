@@ -39,6 +39,10 @@ struct mhd_solver {
     int device;
     bool cmax_valid;      // parts hold the CFL maxima of the current state (from the last step)
     bool bound;           // buffers live in a caller-owned workspace (mhd_bind_workspace)
+    // full steps replayed from HIP graphs, one per sweep order (s mod 3)
+    bool graphs;
+    hipGraphExec_t exec[3];
+    double exec_cfl[3];
     // optional per-kernel timing with HIP events on the handle's stream
     bool timing;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[MHD_K_COUNT];
@@ -164,21 +168,71 @@ int cfl_parts(mhd_solver* h)
                  "cfl launch");
 }
 
+void drop_graphs(mhd_solver* h)
+{
+    for (int q = 0; q < 3; q++) {
+        if (h->exec[q]) (void)hipGraphExecDestroy(h->exec[q]);
+        h->exec[q] = nullptr;
+    }
+}
+
+// One full step (the dt rule on the previous step's c_max slots, then the 12
+// sweeps) captured in a graph for sweep order q and launched; captured again
+// when cfl changes.
+template <typename T>
+int graph_step(mhd_solver* h, int q, double cfl)
+{
+    if (!h->exec[q] || h->exec_cfl[q] != cfl) {
+        if (h->exec[q]) {
+            HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
+            (void)hipGraphExecDestroy(h->exec[q]);
+            h->exec[q] = nullptr;
+        }
+        HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        hipError_t e = mhd::launch_finish(h->parts, h->nparts, 0, cfl, h->ctl, h->stream);
+        int rc = e == hipSuccess ? sweeps<T>(h, h->s, -1.0, true) : hip_fail(e, "dt launch");
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(h->stream, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+        e2 = hipGraphInstantiate(&h->exec[q], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e2 != hipSuccess) {
+            h->exec[q] = nullptr;
+            return hip_fail(e2, "hipGraphInstantiate");
+        }
+        h->exec_cfl[q] = cfl;
+    }
+    HIPCHK(hipGraphLaunch(h->exec[q], h->stream), "hipGraphLaunch");
+    return MHD_OK;
+}
+
 // Full steps. The time-step rule runs on c_max of the current state; its
 // per-workgroup maxima come from the previous step's last fluid sweep, or from
-// a standalone pass after the state was replaced.
+// a standalone pass after the state was replaced. On a stream of its own (not
+// the null stream), with per-kernel timing off and the state in copy 0, a
+// step is replayed from its sweep order's graph.
 template <typename T>
 int full_steps(mhd_solver* h, int n, double cfl)
 {
     for (int k = 0; k < n; k++) {
         int rc;
-        if (!h->cmax_valid && (rc = cfl_parts<T>(h))) return rc;
-        rc = timed(h, MHD_K_CFL,
-                   [&] { return mhd::launch_finish(h->parts, h->nparts, 0, cfl, h->ctl, h->stream); },
-                   "dt launch");
-        if (rc) return rc;
-        rc = sweeps<T>(h, h->s, -1.0, true);
-        if (rc) return rc;
+        const bool replay = h->graphs && h->cmax_valid && h->stream != nullptr && !h->timing && h->ucur == 0 &&
+                            h->bcur == 0;
+        if (replay) {
+            if ((rc = graph_step<T>(h, (int)(h->s % 3), cfl))) return rc;
+        } else {
+            if (!h->cmax_valid && (rc = cfl_parts<T>(h))) return rc;
+            rc = timed(h, MHD_K_CFL,
+                       [&] { return mhd::launch_finish(h->parts, h->nparts, 0, cfl, h->ctl, h->stream); },
+                       "dt launch");
+            if (rc) return rc;
+            rc = sweeps<T>(h, h->s, -1.0, true);
+            if (rc) return rc;
+        }
         h->cmax_valid = true;
         h->s += 1;
     }
@@ -271,6 +325,11 @@ int mhd_create(int nx, int ny, int nz, double gamma, int bc, int dtype, mhd_t** 
     h->s = 0;
     h->cmax_valid = false;
     h->bound = false;
+    h->graphs = true;
+    for (int q = 0; q < 3; q++) {
+        h->exec[q] = nullptr;
+        h->exec_cfl[q] = 0.0;
+    }
     h->timing = false;
     for (int k = 0; k < MHD_K_COUNT; k++) {
         h->total_ms[k] = 0.0;
@@ -322,6 +381,7 @@ int mhd_destroy(mhd_t* h)
     if (!h) return MHD_OK;
     (void)set_current(h);
     (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
     if (!h->bound) {
         (void)hipFree(h->u[0]);
         (void)hipFree(h->u[1]);
@@ -363,6 +423,7 @@ int mhd_bind_workspace(mhd_t* h, void* dev, size_t bytes)
         (void)hipFree(h->ctl);
         (void)hipFree(h->parts);
     }
+    drop_graphs(h);   // they address the old buffers
     h->u[0] = base + offs[0];
     h->u[1] = base + offs[1];
     h->b[0] = base + offs[2];
@@ -373,6 +434,16 @@ int mhd_bind_workspace(mhd_t* h, void* dev, size_t bytes)
     h->s = 0;
     h->cmax_valid = false;
     h->bound = true;
+    return MHD_OK;
+}
+
+int mhd_set_graphs(mhd_t* h, int enable)
+{
+    if (int rc = check(h)) return rc;
+    if (int rc = set_current(h)) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
+    if (!enable) drop_graphs(h);
+    h->graphs = enable != 0;
     return MHD_OK;
 }
 

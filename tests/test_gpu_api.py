@@ -225,3 +225,40 @@ def test_bound_workspace_equals_owned_memory(B):
             assert np.array_equal(got, ref.get_state())
         ws.zero_()           # still the caller's memory after the handle is gone
         torch.cuda.synchronize()
+
+
+def test_graph_replay_equals_direct_launches(B):
+    """Full steps replayed from graphs (a stream of its own) against the same
+    steps launched one by one: identical states after every call, across all
+    three sweep orders, a change of cfl (new capture) and sub-operation calls
+    in between (which leave the state in the other copy, so the step runs
+    without the graph)."""
+    import torch
+
+    nx, ny, nz = 36, 28, 20
+    s = P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 48)
+    stream = torch.cuda.Stream()
+    note("graph replay")
+    for dtype in (B.MHD_F64, B.MHD_F32):
+        states = []
+        for graphs in (True, False):
+            seq = []
+            with B.Solver(nx, ny, nz, H.GAMMA53, 1, dtype) as sv:
+                B.mhd_set_stream(sv.h, stream)
+                B.mhd_set_graphs(sv.h, graphs)
+                sv.set_state(s)
+                for k in range(7):
+                    sv.step(1)
+                    seq.append(sv.get_state())
+                sv.step(2, 0.5)
+                seq.append(sv.get_state())
+                B.mhd_fluid_sweep(sv.h, 1, 0.05)
+                sv.step(2)
+                seq.append(sv.get_state())
+                seq.append(sv.time())
+            states.append(seq)
+        for a, b in zip(*states):
+            if isinstance(a, tuple):
+                assert a == b
+            else:
+                assert np.array_equal(a, b)
