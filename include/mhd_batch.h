@@ -15,9 +15,9 @@
  * Problems whose step counters agree modulo 3 run the same sweep order and
  * form one cohort; each cohort runs 13 launches per full step (the per-problem
  * dt rule and 12 sweeps), captured once in a HIP graph per sweep order and
- * replayed. The autotuner picks, per grid shape and sweep kind, the tile
- * shape (chunk length along the sweep for y/z sweeps, rows per workgroup for
- * x sweeps) that runs fastest on the device; tiles never change results.
+ * replayed. The autotuner picks, per grid shape and y/z sweep kind, the
+ * chunk length along the sweep that runs fastest on the device (x sweeps
+ * have a single shape); tiles never change results.
  *
  * Memory: each problem lives in one device block of
  * mhd_batch_problem_bytes(nx, ny, nz, dtype) bytes (two state copies, its
@@ -131,8 +131,8 @@ int mhd_batch_set_graphs(mhd_batch_t* b, int enable);
 int mhd_batch_autotune(mhd_batch_t* b, int reps);
 
 /* Tile parameters in use for one problem and kind (MHD_K_* of mhd.h):
- * p0 = chunk length (y/z sweeps), segment length (x sweeps) or workgroup
- * count (c_max pass); p1 = rows per workgroup (x sweeps), else 0. */
+ * p0 = chunk length (y/z sweeps) or workgroup count (c_max pass), 0 for the
+ * x sweeps (a single shape); p1 = 0. */
 int mhd_batch_tile(mhd_batch_t* b, int id, int kind, int* p0, int* p1);
 
 #ifdef __cplusplus

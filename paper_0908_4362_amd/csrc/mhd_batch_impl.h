@@ -52,32 +52,27 @@ __global__ void __launch_bounds__(64 * MW) ct_march_batch(const BJob* __restrict
 }
 
 template <typename T, bool CFL>
-__global__ void __launch_bounds__((x_threads<T, false>())) fluid_x_batch(const BJob* __restrict__ jobs,
-                                                                         const TileDesc* __restrict__ td, int njobs,
-                                                                         int iu, int ib)
+__global__ void __launch_bounds__(256) fluid_x_batch(const BJob* __restrict__ jobs, const TileDesc* __restrict__ td,
+                                                     int njobs, int iu, int ib)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int j = find_job(td, njobs, blockIdx.x);
     const BJob& J = jobs[j];
     const Grid g = J.g;
     const unsigned lb = blockIdx.x - td[j].first;
     fluid_x_body<T, CFL>(static_cast<const T*>(J.u[iu]), static_cast<T*>(J.u[iu ^ 1]), static_cast<const T*>(J.b[ib]),
-                         g, (T)J.gamma, J.ctl, -1.0, td[j].p0, td[j].p1, lb, J.parts + lb,
-                         reinterpret_cast<T*>(smem_raw));
+                         g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
 }
 
 template <typename T>
-__global__ void __launch_bounds__((x_threads<T, true>())) ct_x_batch(const BJob* __restrict__ jobs,
-                                                                     const TileDesc* __restrict__ td, int njobs,
-                                                                     int iu, int ib)
+__global__ void __launch_bounds__(256) ct_x_batch(const BJob* __restrict__ jobs, const TileDesc* __restrict__ td,
+                                                  int njobs, int iu, int ib)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int j = find_job(td, njobs, blockIdx.x);
     const BJob& J = jobs[j];
     const Grid g = J.g;
     const unsigned lb = blockIdx.x - td[j].first;
     ct_x_body<T>(static_cast<const T*>(J.u[iu]), static_cast<const T*>(J.b[ib]), static_cast<T*>(J.b[ib ^ 1]), g,
-                 J.ctl, -1.0, td[j].p0, td[j].p1, lb, reinterpret_cast<T*>(smem_raw));
+                 J.ctl, -1.0, lb);
 }
 
 template <typename T>
@@ -101,8 +96,8 @@ void tile_default(const Grid& g, int kind, int* p0, int* p1)
     *p1 = 0;
     switch (kind) {
     case KIND_CFL: *p0 = reduce_blocks(g); break;
-    case KIND_FLUID_X: x_tile(g, GF, x_threads<T, false>() * x_passes<T, false>(), *p0, *p1); break;
-    case KIND_CT_X: x_tile(g, GB, x_threads<T, true>() * x_passes<T, true>(), *p0, *p1); break;
+    case KIND_FLUID_X:
+    case KIND_CT_X: *p0 = 0; break;   // one shape: wavefronts of 64 cells along x
     case KIND_FLUID_Y: *p0 = march_chunk(g, 1, GF); break;
     case KIND_FLUID_Z: *p0 = march_chunk(g, 2, GF); break;
     case KIND_CT_Y: *p0 = march_chunk(g, 1, GB); break;
@@ -111,9 +106,9 @@ void tile_default(const Grid& g, int kind, int* p0, int* p1)
 }
 
 // Candidates: march chunks of the whole pencil down to an eighth of it (never
-// shorter than twice the ghost depth, which would be mostly warm-up); x
-// workgroups of 1, 2, 4, 8 or as many rows as fit. The CFL pass runs only
-// when a batch changes, so it keeps its default.
+// shorter than twice the ghost depth, which would be mostly warm-up). The x
+// sweeps have a single shape, and the CFL pass runs only when a batch
+// changes, so both keep their default.
 template <typename T>
 void tile_candidates(const Grid& g, int kind, std::vector<std::pair<int, int>>& out)
 {
@@ -126,20 +121,7 @@ void tile_candidates(const Grid& g, int kind, std::vector<std::pair<int, int>>& 
         out.emplace_back(a, b);
     };
     add(d0, d1);
-    if (kind == KIND_CFL) return;
-    if (kind == KIND_FLUID_X || kind == KIND_CT_X) {
-        const int ghost = kind == KIND_FLUID_X ? GF : GB;
-        const int cap = kind == KIND_FLUID_X ? x_threads<T, false>() * x_passes<T, false>()
-                                             : x_threads<T, true>() * x_passes<T, true>();
-        const int S = d0;
-        const long long nrows = (long long)g.n[1] * g.n[2];
-        long long rmax = cap / (S + 2 * ghost);
-        if (rmax > nrows) rmax = nrows;
-        if (rmax < 1) rmax = 1;
-        for (long long r : {1LL, 2LL, 4LL, 8LL, rmax})
-            if (r <= rmax) add(S, (int)r);
-        return;
-    }
+    if (kind == KIND_CFL || kind == KIND_FLUID_X || kind == KIND_CT_X) return;
     const int axis = (kind == KIND_FLUID_Y || kind == KIND_CT_Y) ? 1 : 2;
     const int ghost = (kind == KIND_FLUID_Y || kind == KIND_FLUID_Z) ? GF : GB;
     const int nd = g.n[axis];
@@ -154,8 +136,8 @@ unsigned tile_blocks(const Grid& g, int kind, int p0, int p1)
 {
     switch (kind) {
     case KIND_CFL: return (unsigned)p0;
-    case KIND_FLUID_X:
-    case KIND_CT_X: return x_blocks(g, p0, p1);
+    case KIND_FLUID_X: return x_wave_blocks(g);
+    case KIND_CT_X: return ct_x_wave_blocks(g);
     case KIND_FLUID_Y:
     case KIND_CT_Y: return march_blocks(g, 1, p0);
     default: return march_blocks(g, 2, p0);
@@ -163,11 +145,9 @@ unsigned tile_blocks(const Grid& g, int kind, int p0, int p1)
 }
 
 template <typename T>
-size_t tile_lds(int kind, int p0, int p1)
+size_t tile_lds(int, int, int)
 {
-    if (kind == KIND_FLUID_X) return sizeof(T) * 10 * (size_t)p1 * (p0 + 2 * GF);
-    if (kind == KIND_CT_X) return sizeof(T) * 12 * (size_t)p1 * (p0 + 2 * GB);
-    return 0;
+    return 0;   // no kernel of the step uses dynamic LDS
 }
 
 template <typename T>
@@ -180,11 +160,9 @@ hipError_t launch_batch(int kind, bool cfl_parts, const BJob* jobs, const TileDe
     case KIND_CFL: hipLaunchKernelGGL((cfl_batch<T>), dim3(nb), dim3(RB), 0, s, jobs, td, njobs, iu, ib); break;
     case KIND_FLUID_X:
         if (cfl_parts)
-            hipLaunchKernelGGL((fluid_x_batch<T, true>), dim3(nb), dim3(x_threads<T, false>()), lds, s, jobs, td,
-                               njobs, iu, ib);
+            hipLaunchKernelGGL((fluid_x_batch<T, true>), dim3(nb), dim3(256), 0, s, jobs, td, njobs, iu, ib);
         else
-            hipLaunchKernelGGL((fluid_x_batch<T, false>), dim3(nb), dim3(x_threads<T, false>()), lds, s, jobs, td,
-                               njobs, iu, ib);
+            hipLaunchKernelGGL((fluid_x_batch<T, false>), dim3(nb), dim3(256), 0, s, jobs, td, njobs, iu, ib);
         break;
     case KIND_FLUID_Y:
         if (cfl_parts)
@@ -199,7 +177,7 @@ hipError_t launch_batch(int kind, bool cfl_parts, const BJob* jobs, const TileDe
             hipLaunchKernelGGL((fluid_march_batch<T, 2, false>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
         break;
     case KIND_CT_X:
-        hipLaunchKernelGGL((ct_x_batch<T>), dim3(nb), dim3(x_threads<T, true>()), lds, s, jobs, td, njobs, iu, ib);
+        hipLaunchKernelGGL((ct_x_batch<T>), dim3(nb), dim3(256), 0, s, jobs, td, njobs, iu, ib);
         break;
     case KIND_CT_Y: hipLaunchKernelGGL((ct_march_batch<T, 1>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib); break;
     case KIND_CT_Z: hipLaunchKernelGGL((ct_march_batch<T, 2>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib); break;

@@ -64,12 +64,7 @@ hipError_t launch_finish(const unsigned long long* parts, int nparts, int what, 
 size_t reduce_capacity(const Grid& g)
 {
     size_t cap = (size_t)reduce_blocks(g);
-    int S, R;
-    for (int xcap : {x_threads<double, false>() * x_passes<double, false>(),
-                     x_threads<float, false>() * x_passes<float, false>()}) {
-        x_tile(g, GF, xcap, S, R);
-        cap = std::max(cap, (size_t)x_blocks(g, S, R));
-    }
+    cap = std::max(cap, (size_t)x_wave_blocks(g));
     for (int axis = 1; axis <= 2; axis++)
         cap = std::max(cap, (size_t)march_blocks(g, axis, march_chunk(g, axis, GF)));
     return cap;

@@ -14,8 +14,9 @@
 // Sweeps along y and z march through each pencil: a thread owns one x column
 // (64 consecutive x per wavefront, so every load and store is coalesced) and
 // walks along the sweep axis keeping the stencil window in registers; a pencil
-// is cut into chunks that re-run a short warm-up. Sweeps along x stage one
-// pencil segment per workgroup in LDS, one cell per thread.
+// is cut into chunks that re-run a short warm-up. Sweeps along x hold 64
+// consecutive cells of a row in the lanes of one wavefront, one cell per lane,
+// and exchange stencil neighbours with cross-lane shuffles.
 #pragma once
 #include <algorithm>
 #include <type_traits>
@@ -61,6 +62,10 @@ __device__ __forceinline__ T vanleer(T a, T b)
 template <typename T>
 __device__ __forceinline__ T cfl_speed(T rho, T mx, T my, T mz, T en, T bx, T by, T bz, T gamma)
 {
+    // no contraction: every kernel that evaluates it (the c_max pass, the
+    // fluid sweeps that store c_max slots) must get the same bits, so that a
+    // run resumed from a stored state takes the same dt
+#pragma clang fp contract(off)
     const T bb = bx * bx + by * by + bz * bz;
     if constexpr (kExact<T>) {
         const T vx = mx / rho, vy = my / rho, vz = mz / rho;
@@ -585,365 +590,191 @@ __global__ void __launch_bounds__(64 * MW) ct_march(const T* __restrict__ uf, co
 }
 
 // ---------------------------------------------------------------------------
-// fluid_x: one workgroup stages R rows x (S + 6) cells in LDS, one cell per
-// thread per pass (at most two passes), and updates S cells per row.
-// Workgroup shape of the x kernels: threads, and passes (cells per thread).
-// One pass of 320 threads covers a 256-cell row with its ghosts; FP32 fluid
-// sweeps measured faster with two passes of 256 threads.
-template <typename T, bool CT>
-constexpr int x_threads()
-{
-    return (kExact<T> || CT) ? 320 : 256;
-}
-template <typename T, bool CT>
-constexpr int x_passes()
-{
-    return (kExact<T> || CT) ? 1 : 2;
-}
+// fluid_x: a wavefront holds 64 consecutive cells of one row in its lanes (3
+// ghost cells each side, so it updates XW = 58 of them) and takes every
+// stencil neighbour from the adjacent lane with a cross-lane shuffle; the
+// wavefronts are independent (no LDS, no barrier until the final c_max
+// reduction). Workgroups of 4 wavefronts; logical workgroup lb covers
+// wavefronts 4 lb .. 4 lb + 3, rows fastest in segments along x. (Staging
+// rows in LDS with a barrier per stage measured 24 % slower.)
+constexpr int XW = 64 - 2 * GF;
 
 template <typename T, bool CFL>
 __device__ __forceinline__ void fluid_x_body(const T* __restrict__ uin, T* __restrict__ uout,
                                              const T* __restrict__ bf, const Grid& g, T gamma,
-                                             const Ctl* __restrict__ ctl, double dt_arg, int S, int R, unsigned lb,
-                                             unsigned long long* __restrict__ part, T* sr)
+                                             const Ctl* __restrict__ ctl, double dt_arg, unsigned lb,
+                                             unsigned long long* __restrict__ part)
 {
-    constexpr int XT = x_threads<T, false>(), XP = x_passes<T, false>();
-    const int Ext = S + 2 * GF;
-    const int ncell = R * Ext;
-    T* sl = sr + 5 * ncell;
+    const int lane = threadIdx.x & 63;
     const int nx = g.n[0], ny = g.n[1];
+    const int wpr = (nx + XW - 1) / XW;   // wavefronts per row
     const long long nrows = (long long)ny * g.n[2];
+    const long long wave = (long long)lb * 4 + (threadIdx.x >> 6);
+    const long long row = wave / wpr;
+    const int seg = (int)(wave - row * wpr);
+    const bool live = row < nrows;        // wavefronts past the last row only join the block reduction
+    const long long rowc = live ? row : 0;
+    const int j = (int)(rowc % ny), k = (int)(rowc / ny);
+    const int xu = seg * XW - GF + lane;  // position along x before the boundary map
+    const int x = wrap_idx(xu, nx, g.bc), xn = wrap_idx(xu + 1, nx, g.bc);
     const long long N = g.N;
-    const unsigned nseg = (nx + S - 1) / S;
-    // segments fastest, then row groups
-    const int o0 = (lb % nseg) * S;
-    const long long row0 = (long long)(lb / nseg) * R;
+    const long long rb = (long long)nx * (j + (long long)ny * k);
+    const long long c = rb + x;
+    const long long cy = (long long)nx * (wrap_idx(j + 1, ny, g.bc) + (long long)ny * k) + x;
+    const long long cz = (long long)nx * (j + (long long)ny * wrap_idx(k + 1, g.n[2], g.bc)) + x;
     const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
     const bool frozen = ctl->status != 0;
 
-    T u[XP][5], b[XP][3], rr[XP][5], ll[XP][5];
-    int m_[XP], slot[XP];
-    long long cidx[XP];
-    bool act[XP];
+    T u[5], b[3], rr[5], ll[5];
 #pragma unroll
-    for (int p = 0; p < XP; p++) {
-        const int idx = threadIdx.x + p * XT;
-        const int rl = idx / Ext;
-        const int m = idx - rl * Ext;
-        const long long row = row0 + rl;
-        act[p] = idx < ncell && row < nrows;
-        m_[p] = m;
-        slot[p] = idx;
-        cidx[p] = 0;
-        if (act[p]) {
-            const int j = (int)(row % ny);
-            const int k = (int)(row / ny);
-            const int x = wrap_idx(o0 - GF + m, nx, g.bc);
-            const int xn = wrap_idx(o0 - GF + m + 1, nx, g.bc);
-            const long long rb = (long long)nx * (j + (long long)ny * k);
-            const long long c = rb + x;
-            const long long cy = (long long)nx * (wrap_idx(j + 1, ny, g.bc) + (long long)ny * k) + x;
-            const long long cz = (long long)nx * (j + (long long)ny * wrap_idx(k + 1, g.n[2], g.bc)) + x;
-            cidx[p] = c;
-            u[p][0] = uin[c];
-            u[p][1] = uin[N + c];
-            u[p][2] = uin[2 * N + c];
-            u[p][3] = uin[3 * N + c];
-            u[p][4] = uin[4 * N + c];
-            b[p][0] = T(0.5) * (bf[c] + bf[rb + xn]);
-            b[p][1] = T(0.5) * (bf[N + c] + bf[N + cy]);
-            b[p][2] = T(0.5) * (bf[2 * N + c] + bf[2 * N + cz]);
-            movers(u[p], b[p], gamma, rr[p], ll[p]);
+    for (int q = 0; q < 5; q++) u[q] = uin[q * N + c];
+    b[0] = T(0.5) * (bf[c] + bf[rb + xn]);
+    b[1] = T(0.5) * (bf[N + c] + bf[N + cy]);
+    b[2] = T(0.5) * (bf[2 * N + c] + bf[2 * N + cz]);
+    movers(u, b, gamma, rr, ll);
+    // stage 1: first-order flux at x + 1/2, half step, movers of the half state
+    T f[5], uh[5], rp[5], lp[5];
 #pragma unroll
-            for (int q = 0; q < 5; q++) {
-                sr[q * ncell + idx] = rr[p][q];
-                sl[q * ncell + idx] = ll[p][q];
-            }
-        }
+    for (int q = 0; q < 5; q++) f[q] = rr[q] - __shfl_down(ll[q], 1);
+#pragma unroll
+    for (int q = 0; q < 5; q++) uh[q] = u[q] - (dt * T(0.5)) * (f[q] - __shfl_up(f[q], 1));
+    movers(uh, b, gamma, rp, lp);
+    // stage 2: limited movers (eq. limiter on half-differences)
+    T Rr[5], Ll[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+        const T a = __shfl_up(rp[q], 1), c0 = rp[q], d = __shfl_down(rp[q], 1);
+        Rr[q] = c0 + vanleer((c0 - a) / T(2), (d - c0) / T(2));
+        const T al = __shfl_up(lp[q], 1), cl = lp[q], dl = __shfl_down(lp[q], 1);
+        Ll[q] = cl - vanleer((cl - al) / T(2), (dl - cl) / T(2));
     }
-    __syncthreads();
-    // stage 1: half step of cells m in [1, Ext-1), movers of the half state
-    T rp[XP][5], lp[XP][5];
+    // full update of lanes GF .. GF + XW - 1 (eq. Delta_u_full)
+    T fp[5], un[5];
 #pragma unroll
-    for (int p = 0; p < XP; p++) {
-        if (act[p] && m_[p] >= 1 && m_[p] < Ext - 1) {
-            const int s = slot[p];
-            T uh[5];
+    for (int q = 0; q < 5; q++) fp[q] = Rr[q] - __shfl_down(Ll[q], 1);
 #pragma unroll
-            for (int q = 0; q < 5; q++) {
-                const T fp = rr[p][q] - sl[q * ncell + s + 1];
-                const T fm = sr[q * ncell + s - 1] - ll[p][q];
-                uh[q] = u[p][q] - (dt * T(0.5)) * (fp - fm);
-            }
-            movers(uh, b[p], gamma, rp[p], lp[p]);
-        }
+    for (int q = 0; q < 5; q++) {
+        const T fm = __shfl_up(fp[q], 1);
+        un[q] = frozen ? u[q] : u[q] - dt * (fp[q] - fm);
     }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < XP; p++) {
-        if (act[p] && m_[p] >= 1 && m_[p] < Ext - 1) {
-#pragma unroll
-            for (int q = 0; q < 5; q++) {
-                sr[q * ncell + slot[p]] = rp[p][q];
-                sl[q * ncell + slot[p]] = lp[p][q];
-            }
-        }
-    }
-    __syncthreads();
-    // stage 2: limited movers at cells m in [2, Ext-2)
-    T Rr[XP][5], Ll[XP][5];
-#pragma unroll
-    for (int p = 0; p < XP; p++) {
-        if (act[p] && m_[p] >= 2 && m_[p] < Ext - 2) {
-            const int s = slot[p];
-#pragma unroll
-            for (int q = 0; q < 5; q++) {
-                const T a = sr[q * ncell + s - 1], c0 = rp[p][q], d = sr[q * ncell + s + 1];
-                Rr[p][q] = c0 + vanleer((c0 - a) / T(2), (d - c0) / T(2));
-                const T al = sl[q * ncell + s - 1], cl = lp[p][q], dl = sl[q * ncell + s + 1];
-                Ll[p][q] = cl - vanleer((cl - al) / T(2), (dl - cl) / T(2));
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < XP; p++) {
-        if (act[p] && m_[p] >= 2 && m_[p] < Ext - 2) {
-#pragma unroll
-            for (int q = 0; q < 5; q++) {
-                sr[q * ncell + slot[p]] = Rr[p][q];
-                sl[q * ncell + slot[p]] = Ll[p][q];
-            }
-        }
-    }
-    __syncthreads();
-    // full update of the S owned cells per row (eq. Delta_u_full)
     unsigned long long best = 0ull;
+    if (live && lane >= GF && lane < GF + XW && xu < nx) {
 #pragma unroll
-    for (int p = 0; p < XP; p++) {
-        const int m = m_[p];
-        const int x = o0 - GF + m;
-        if (act[p] && m >= GF && m < Ext - GF && x < nx) {
-            const int s = slot[p];
-            const long long c = cidx[p];
-            T un[5];
-#pragma unroll
-            for (int q = 0; q < 5; q++) {
-                const T fp = Rr[p][q] - sl[q * ncell + s + 1];
-                const T fm = sr[q * ncell + s - 1] - Ll[p][q];
-                un[q] = frozen ? u[p][q] : u[p][q] - dt * (fp - fm);
-                uout[q * N + c] = un[q];
-            }
-            if constexpr (CFL) {
-                const T cc = cfl_speed(un[0], un[1], un[2], un[3], un[4], b[p][0], b[p][1], b[p][2], gamma);
-                const unsigned long long bits = speed_bits(cc);
-                best = bits > best ? bits : best;
-            }
+        for (int q = 0; q < 5; q++) uout[q * N + c] = un[q];
+        if constexpr (CFL) {
+            const T cc = cfl_speed(un[0], un[1], un[2], un[3], un[4], b[0], b[1], b[2], gamma);
+            best = speed_bits(cc);
         }
     }
-    if constexpr (CFL) block_max_to_part<XT>(best, threadIdx.x, part);
+    if constexpr (CFL) block_max_to_part<256>(best, threadIdx.x, part);
 }
 
 template <typename T, bool CFL>
-__global__ void __launch_bounds__((x_threads<T, false>())) fluid_x_lds(const T* __restrict__ uin, T* __restrict__ uout,
-                                                  const T* __restrict__ bf, Grid g, T gamma,
-                                                  const Ctl* __restrict__ ctl, double dt_arg, int S, int R,
-                                                  unsigned long long* __restrict__ parts)
+__global__ void __launch_bounds__(256) fluid_x_wave(const T* __restrict__ uin, T* __restrict__ uout,
+                                                    const T* __restrict__ bf, Grid g, T gamma,
+                                                    const Ctl* __restrict__ ctl, double dt_arg,
+                                                    unsigned long long* __restrict__ parts)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const unsigned lb = blockIdx.x;
-    fluid_x_body<T, CFL>(uin, uout, bf, g, gamma, ctl, dt_arg, S, R, lb, parts + blockIdx.x,
-                         reinterpret_cast<T*>(smem_raw));
+    fluid_x_body<T, CFL>(uin, uout, bf, g, gamma, ctl, dt_arg, blockIdx.x, parts + blockIdx.x);
 }
 
-// B_{y->x}, B_{z->x}: one workgroup stages R rows x (S + 8) cells in LDS and
-// runs the four EMF pencils of each row (own and +y for B_y, own and +z for
-// B_z) stage by stage.
+static unsigned x_wave_blocks(const Grid& g)
+{
+    const long long waves = (long long)g.n[1] * g.n[2] * ((g.n[0] + XW - 1) / XW);
+    return (unsigned)((waves + 3) / 4);
+}
+
+// B_{y->x}, B_{z->x}: a wavefront holds 64 consecutive cells of one row (4
+// ghost cells each side, so it updates XWC = 56) and runs the four EMF
+// pencils of the row (own and +y face for B_y, own and +z face for B_z) stage
+// by stage, with cross-lane shuffles for the neighbours along x.
+constexpr int XWC = 64 - 2 * GB;
+
 template <typename T>
 __device__ __forceinline__ void ct_x_body(const T* __restrict__ uf, const T* __restrict__ bin,
                                           T* __restrict__ bout, const Grid& g, const Ctl* __restrict__ ctl,
-                                          double dt_arg, int S, int R, unsigned lb, T* sA)
+                                          double dt_arg, unsigned lb)
 {
-    constexpr int XT = x_threads<T, true>(), XP = x_passes<T, true>();
-    // sA: 4 x ncell: velocities, then v B^{t+dt/2}
-    const int Ext = S + 2 * GB;
-    const int ncell = R * Ext;
-    T* sB = sA + 4 * ncell;                     // 4 x ncell: v B, then limited slopes
-    T* sC = sB + 4 * ncell;                     // 4 x ncell: first-order EMF, then EMF
+    const int lane = threadIdx.x & 63;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int wpr = (nx + XWC - 1) / XWC;
     const long long nrows = (long long)ny * nz;
+    const long long wave = (long long)lb * 4 + (threadIdx.x >> 6);
+    const long long row = wave / wpr;
+    if (row >= nrows) return;   // no barrier follows: whole wavefronts past the last row leave
+    const int seg = (int)(wave - row * wpr);
+    const int j = (int)(row % ny), k = (int)(row / ny);
+    const int xu = seg * XWC - GB + lane;
+    const int x = wrap_idx(xu, nx, g.bc);
+    const int jm = wrap_idx(j - 1, ny, g.bc), jp = wrap_idx(j + 1, ny, g.bc);
+    const int km = wrap_idx(k - 1, nz, g.bc), kp = wrap_idx(k + 1, nz, g.bc);
     const long long N = g.N;
-    const unsigned nseg = (nx + S - 1) / S;
-    // segments fastest, then row groups
-    const int o0 = (lb % nseg) * S;
-    const long long row0 = (long long)(lb / nseg) * R;
+    const long long c = (long long)nx * (j + (long long)ny * k) + x;
+    const long long cym = (long long)nx * (jm + (long long)ny * k) + x;
+    const long long cyp = (long long)nx * (jp + (long long)ny * k) + x;
+    const long long czm = (long long)nx * (j + (long long)ny * km) + x;
+    const long long czp = (long long)nx * (j + (long long)ny * kp) + x;
     const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
     const bool frozen = ctl->status != 0;
 
-    // pencil p: 0 = B_y own, 1 = B_y at +y, 2 = B_z own, 3 = B_z at +z
-    T vh[XP][4], Bk[XP][4], vv[XP][4], ev[XP][4];
-    int m_[XP], slot[XP];
-    long long cidx[XP];
-    bool act[XP];
+    // pencil e: 0 = B_y own, 1 = B_y at +y, 2 = B_z own, 3 = B_z at +z
+    T vh[4], Bk[4];
+    const T r0 = uf[c], m0 = uf[N + c];
+    vh[0] = (uf[N + cym] + m0) / (uf[cym] + r0);
+    vh[1] = (m0 + uf[N + cyp]) / (r0 + uf[cyp]);
+    vh[2] = (uf[N + czm] + m0) / (uf[czm] + r0);
+    vh[3] = (m0 + uf[N + czp]) / (r0 + uf[czp]);
+    Bk[0] = bin[N + c];
+    Bk[1] = bin[N + cyp];
+    Bk[2] = bin[2 * N + c];
+    Bk[3] = bin[2 * N + czp];
+    T G[4], gm[4];
 #pragma unroll
-    for (int p = 0; p < XP; p++) {
-        const int idx = threadIdx.x + p * XT;
-        const int rl = idx / Ext;
-        const int m = idx - rl * Ext;
-        const long long row = row0 + rl;
-        act[p] = idx < ncell && row < nrows;
-        m_[p] = m;
-        slot[p] = idx;
-        cidx[p] = 0;
-        if (act[p]) {
-            const int j = (int)(row % ny);
-            const int k = (int)(row / ny);
-            const int x = wrap_idx(o0 - GB + m, nx, g.bc);
-            const int jm = wrap_idx(j - 1, ny, g.bc), jp = wrap_idx(j + 1, ny, g.bc);
-            const int km = wrap_idx(k - 1, nz, g.bc), kp = wrap_idx(k + 1, nz, g.bc);
-            const long long c = (long long)nx * (j + (long long)ny * k) + x;
-            const long long cym = (long long)nx * (jm + (long long)ny * k) + x;
-            const long long cyp = (long long)nx * (jp + (long long)ny * k) + x;
-            const long long czm = (long long)nx * (j + (long long)ny * km) + x;
-            const long long czp = (long long)nx * (j + (long long)ny * kp) + x;
-            cidx[p] = c;
-            const T r0 = uf[c], m0 = uf[N + c];
-            vh[p][0] = (uf[N + cym] + m0) / (uf[cym] + r0);
-            vh[p][1] = (m0 + uf[N + cyp]) / (r0 + uf[cyp]);
-            vh[p][2] = (uf[N + czm] + m0) / (uf[czm] + r0);
-            vh[p][3] = (m0 + uf[N + czp]) / (r0 + uf[czp]);
-            Bk[p][0] = bin[N + c];
-            Bk[p][1] = bin[N + cyp];
-            Bk[p][2] = bin[2 * N + c];
-            Bk[p][3] = bin[2 * N + czp];
-#pragma unroll
-            for (int e = 0; e < 4; e++) sA[e * ncell + idx] = vh[p][e];
-        }
+    for (int e = 0; e < 4; e++) {
+        // smoothed velocity (eq. averaging_x) and v B
+        const T vv = T(0.25) * (__shfl_up(vh[e], 1) + T(2) * vh[e] + __shfl_down(vh[e], 1));
+        const T qb = vv * Bk[e];
+        // edge velocity and first-order upwind EMF at x + 1/2
+        const T ev = T(0.5) * (vv + __shfl_down(vv, 1));
+        const T qbn = __shfl_down(qb, 1);
+        const T g1 = ev > T(0) ? qb : qbn;
+        // half step and v B^{t+dt/2}
+        const T bhalf = Bk[e] - (dt * T(0.5)) * (g1 - __shfl_up(g1, 1));
+        const T qh = vv * bhalf;
+        // limited slope and second-order EMF at x + 1/2
+        const T qhm = __shfl_up(qh, 1), qhp = __shfl_down(qh, 1);
+        const T sq = vanleer((qh - qhm) / T(2), (qhp - qh) / T(2));
+        const T sqp = __shfl_down(sq, 1);
+        G[e] = ev > T(0) ? qh + sq : qhp - sqp;
+        gm[e] = __shfl_up(G[e], 1);
     }
-    __syncthreads();
-    // smoothed velocity (eq. averaging_x) and v B at m in [1, Ext-1)
-#pragma unroll
-    for (int p = 0; p < XP; p++) {
-        if (act[p] && m_[p] >= 1 && m_[p] < Ext - 1) {
-            const int s = slot[p];
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                vv[p][e] = T(0.25) * (sA[e * ncell + s - 1] + T(2) * vh[p][e] + sA[e * ncell + s + 1]);
-                sB[e * ncell + s] = vv[p][e] * Bk[p][e];
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < XP; p++) {
-        if (act[p] && m_[p] >= 1 && m_[p] < Ext - 1) {
-#pragma unroll
-            for (int e = 0; e < 4; e++) sA[e * ncell + slot[p]] = vv[p][e];
-        }
-    }
-    __syncthreads();
-    // edge velocity and first-order upwind EMF at m + 1/2, m in [1, Ext-2)
-#pragma unroll
-    for (int p = 0; p < XP; p++) {
-        if (act[p] && m_[p] >= 1 && m_[p] < Ext - 2) {
-            const int s = slot[p];
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                ev[p][e] = T(0.5) * (vv[p][e] + sA[e * ncell + s + 1]);
-                sC[e * ncell + s] = ev[p][e] > T(0) ? sB[e * ncell + s] : sB[e * ncell + s + 1];
-            }
-        }
-    }
-    __syncthreads();
-    // half step and v B^{t+dt/2} at m in [2, Ext-2)
-    T qh[XP][4];
-#pragma unroll
-    for (int p = 0; p < XP; p++) {
-        if (act[p] && m_[p] >= 2 && m_[p] < Ext - 2) {
-            const int s = slot[p];
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const T bhalf = Bk[p][e] - (dt * T(0.5)) * (sC[e * ncell + s] - sC[e * ncell + s - 1]);
-                qh[p][e] = vv[p][e] * bhalf;
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < XP; p++) {
-        if (act[p] && m_[p] >= 2 && m_[p] < Ext - 2) {
-#pragma unroll
-            for (int e = 0; e < 4; e++) sA[e * ncell + slot[p]] = qh[p][e];
-        }
-    }
-    __syncthreads();
-    // limited slopes at m in [3, Ext-3)
-    T sq[XP][4];
-#pragma unroll
-    for (int p = 0; p < XP; p++) {
-        if (act[p] && m_[p] >= 3 && m_[p] < Ext - 3) {
-            const int s = slot[p];
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const T a = sA[e * ncell + s - 1], c0 = qh[p][e], d = sA[e * ncell + s + 1];
-                sq[p][e] = vanleer((c0 - a) / T(2), (d - c0) / T(2));
-                sB[e * ncell + s] = sq[p][e];
-            }
-        }
-    }
-    __syncthreads();
-    // second-order EMF at m + 1/2, m in [3, Ext-4)
-    T G[XP][4];
-#pragma unroll
-    for (int p = 0; p < XP; p++) {
-        if (act[p] && m_[p] >= 3 && m_[p] < Ext - 4) {
-            const int s = slot[p];
-#pragma unroll
-            for (int e = 0; e < 4; e++)
-                G[p][e] = ev[p][e] > T(0) ? qh[p][e] + sq[p][e] : sA[e * ncell + s + 1] - sB[e * ncell + s + 1];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < XP; p++) {
-        if (act[p] && m_[p] >= 3 && m_[p] < Ext - 4) {
-#pragma unroll
-            for (int e = 0; e < 4; e++) sC[e * ncell + slot[p]] = G[p][e];
-        }
-    }
-    __syncthreads();
-    // advection of B_y, B_z and constraint update of B_x for m in [4, Ext-4)
-#pragma unroll
-    for (int p = 0; p < XP; p++) {
-        const int m = m_[p];
-        const int x = o0 - GB + m;
-        if (act[p] && m >= GB && m < Ext - GB && x < nx) {
-            const int s = slot[p];
-            const long long c = cidx[p];
-            const T gm0 = sC[0 * ncell + s - 1], gm1 = sC[1 * ncell + s - 1];
-            const T gm2 = sC[2 * ncell + s - 1], gm3 = sC[3 * ncell + s - 1];
-            const T bx = bin[c];
-            if (frozen) {
-                bout[c] = bx;
-                bout[N + c] = Bk[p][0];
-                bout[2 * N + c] = Bk[p][2];
-            } else {
-                bout[N + c] = Bk[p][0] - dt * (G[p][0] - gm0);
-                bout[2 * N + c] = Bk[p][2] - dt * (G[p][2] - gm2);
-                bout[c] = (bx + dt * (gm1 - gm0)) + dt * (gm3 - gm2);
-            }
+    // advection of B_y, B_z and constraint update of B_x
+    if (lane >= GB && lane < GB + XWC && xu < nx) {
+        const T bx = bin[c];
+        if (frozen) {
+            bout[c] = bx;
+            bout[N + c] = Bk[0];
+            bout[2 * N + c] = Bk[2];
+        } else {
+            bout[N + c] = Bk[0] - dt * (G[0] - gm[0]);
+            bout[2 * N + c] = Bk[2] - dt * (G[2] - gm[2]);
+            bout[c] = (bx + dt * (gm[1] - gm[0])) + dt * (gm[3] - gm[2]);
         }
     }
 }
 
 template <typename T>
-__global__ void __launch_bounds__((x_threads<T, true>())) ct_x_lds(const T* __restrict__ uf, const T* __restrict__ bin,
-                                               T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
-                                               double dt_arg, int S, int R)
+__global__ void __launch_bounds__(256) ct_x_wave(const T* __restrict__ uf, const T* __restrict__ bin,
+                                                 T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
+                                                 double dt_arg)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const unsigned lb = blockIdx.x;
-    ct_x_body<T>(uf, bin, bout, g, ctl, dt_arg, S, R, lb, reinterpret_cast<T*>(smem_raw));
+    ct_x_body<T>(uf, bin, bout, g, ctl, dt_arg, blockIdx.x);
+}
+
+static unsigned ct_x_wave_blocks(const Grid& g)
+{
+    const long long waves = (long long)g.n[1] * g.n[2] * ((g.n[0] + XWC - 1) / XWC);
+    return (unsigned)((waves + 3) / 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -1043,26 +874,6 @@ int march_chunk(const Grid& g, int d, int ghost)
 
 }  // namespace
 
-// one segment per row if it fits cap = threads x passes cells, several rows
-// per workgroup when rows are short
-static void x_tile(const Grid& g, int ghost, int cap, int& S, int& R)
-{
-    const int nx = g.n[0];
-    int nseg = 1;
-    while ((nx + nseg - 1) / nseg + 2 * ghost > cap) nseg++;
-    S = (nx + nseg - 1) / nseg;
-    R = cap / (S + 2 * ghost);
-    if (R < 1) R = 1;
-    const long long nrows = (long long)g.n[1] * g.n[2];
-    if (R > nrows) R = (int)nrows;
-}
-
-static unsigned x_blocks(const Grid& g, int S, int R)
-{
-    const long long nrows = (long long)g.n[1] * g.n[2];
-    return (unsigned)(((nrows + R - 1) / R) * ((g.n[0] + S - 1) / S));
-}
-
 static unsigned march_blocks(const Grid& g, int axis, int chunk)
 {
     const int ta = (axis == 1) ? 2 : 1;
@@ -1094,12 +905,9 @@ static void fluid_launch(int axis, const T* u_in, T* u_out, const T* b, Grid g, 
 {
     unsigned nb;
     if (axis == 0) {
-        int S, R;
-        x_tile(g, GF, x_threads<T, false>() * x_passes<T, false>(), S, R);
-        nb = x_blocks(g, S, R);
-        const size_t lds = sizeof(T) * 10 * (size_t)R * (S + 2 * GF);
-        hipLaunchKernelGGL((fluid_x_lds<T, CFL>), dim3(nb), dim3(x_threads<T, false>()), lds, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
-                           S, R, parts);
+        nb = x_wave_blocks(g);
+        hipLaunchKernelGGL((fluid_x_wave<T, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
+                           parts);
     } else {
         const int chunk = march_chunk(g, axis, GF);
         nb = march_blocks(g, axis, chunk);
@@ -1130,11 +938,7 @@ hipError_t launch_ct(int axis, const T* u, const T* b_in, T* b_out, Grid g, cons
                      hipStream_t s)
 {
     if (axis == 0) {
-        int S, R;
-        x_tile(g, GB, x_threads<T, true>() * x_passes<T, true>(), S, R);
-        const size_t lds = sizeof(T) * 12 * (size_t)R * (S + 2 * GB);
-        hipLaunchKernelGGL((ct_x_lds<T>), dim3(x_blocks(g, S, R)), dim3(x_threads<T, true>()), lds, s, u, b_in, b_out, g, ctl, dt, S,
-                           R);
+        hipLaunchKernelGGL((ct_x_wave<T>), dim3(ct_x_wave_blocks(g)), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt);
     } else {
         const int chunk = march_chunk(g, axis, GB);
         const dim3 grid(march_blocks(g, axis, chunk)), block(64, MW);
