@@ -35,6 +35,60 @@ namespace {
 template <typename T>
 constexpr bool kExact = std::is_same<T, double>::value;
 
+// Division. FP64 quotients must be the correctly rounded ones the oracle
+// gets. The compiler's IEEE division is a Newton-Raphson refinement of the
+// hardware reciprocal followed by a residual correction (Markstein's method),
+// wrapped in range scaling (v_div_scale / v_div_fmas / v_div_fixup) that only
+// acts when an operand or the quotient is near the edge of the exponent range
+// or not finite. The helpers below run the same refinement without that
+// wrapping, so for normal-range operands (every state of a physical run) they
+// give the same bits in 8 instructions instead of 11, and a reciprocal that
+// several quotients share (the divisions by rho of one cell) is refined once.
+// Outside that range (|n| below about 1e-292, a subnormal or zero divisor)
+// a quotient may differ from IEEE division in its last bit or be non-finite.
+struct Recip64 {
+    double y;    // refined reciprocal of d
+    double nd;   // -d
+};
+
+__device__ __forceinline__ Recip64 recip64(double d)
+{
+    const double nd = -d;
+    const double y0 = __builtin_amdgcn_rcp(d);
+    const double e0 = __builtin_fma(nd, y0, 1.0);
+    const double y1 = __builtin_fma(y0, e0, y0);
+    const double e1 = __builtin_fma(nd, y1, 1.0);
+    return {__builtin_fma(y1, e1, y1), nd};
+}
+
+__device__ __forceinline__ double div64(double n, const Recip64& r)
+{
+    const double q = n * r.y;
+    const double rem = __builtin_fma(r.nd, q, n);
+    return __builtin_fma(rem, r.y, q);
+}
+
+// n / d: correctly rounded (normal range) in FP64; in FP32 the hardware
+// reciprocal (1 ulp) times n.
+template <typename T>
+__device__ __forceinline__ T qdiv(T n, T d)
+{
+    if constexpr (kExact<T>)
+        return div64(n, recip64(d));
+    else
+        return n * __builtin_amdgcn_rcpf(d);
+}
+
+// Square root: IEEE in FP64 (the oracle's), the hardware one (1 ulp) in FP32.
+template <typename T>
+__device__ __forceinline__ T qsqrt(T x)
+{
+    if constexpr (kExact<T>)
+        return sqrt(x);
+    else
+        return __builtin_amdgcn_sqrtf(x);
+}
+
 constexpr int GF = 3;  // ghost depth of the fluid sweep
 constexpr int GB = 4;  // ghost depth of the field (CT) sweep
 
@@ -42,8 +96,12 @@ __device__ __forceinline__ int wrap_idx(int i, int n, int bc)
 {
     if ((unsigned)i < (unsigned)n) return i;
     if (bc == 0) {
-        int r = i % n;
-        return r < 0 ? r + n : r;
+        // one period away covers every ghost unless the grid is shorter
+        // than the stencil's reach
+        const int r = i < 0 ? i + n : i - n;
+        if ((unsigned)r < (unsigned)n) return r;
+        const int m = i % n;
+        return m < 0 ? m + n : m;
     }
     return i < 0 ? 0 : n - 1;
 }
@@ -53,7 +111,7 @@ __device__ __forceinline__ T vanleer(T a, T b)
 {
     // eq. limiter; zero when the half-differences differ in sign
     const T ab = a * b;
-    return ab > T(0) ? T(2) * ab / (a + b) : T(0);
+    return ab > T(0) ? qdiv(T(2) * ab, a + b) : T(0);
 }
 
 // CFL speed of one cell, eq. equat_CFL: largest |v| component plus
@@ -68,18 +126,19 @@ __device__ __forceinline__ T cfl_speed(T rho, T mx, T my, T mz, T en, T bx, T by
 #pragma clang fp contract(off)
     const T bb = bx * bx + by * by + bz * bz;
     if constexpr (kExact<T>) {
-        const T vx = mx / rho, vy = my / rho, vz = mz / rho;
+        const Recip64 ri = recip64(rho);
+        const T vx = div64(mx, ri), vy = div64(my, ri), vz = div64(mz, ri);
         const T vv = vx * vx + vy * vy + vz * vz;
         const T p = (gamma - T(1)) * (en - T(0.5) * rho * vv - T(0.5) * bb);
         const T vm = fmax(fabs(vx), fmax(fabs(vy), fabs(vz)));
-        return vm + sqrt(fabs(gamma * p + bb) / rho);
+        return vm + sqrt(div64(fabs(gamma * p + bb), ri));
     } else {
-        const T rinv = T(1) / rho;
+        const T rinv = __builtin_amdgcn_rcpf(rho);
         const T vx = mx * rinv, vy = my * rinv, vz = mz * rinv;
         const T ke = T(0.5) * (mx * vx + my * vy + mz * vz);
         const T p = (gamma - T(1)) * (en - ke - T(0.5) * bb);
         const T vm = fmax(fabs(vx), fmax(fabs(vy), fabs(vz)));
-        return vm + sqrt(fabs(gamma * p + bb) * rinv);
+        return vm + qsqrt(fabs(gamma * p + bb) * rinv);
     }
 }
 
@@ -170,7 +229,8 @@ __device__ __forceinline__ void movers(const T* u, const T* b, T gamma, T* r, T*
     T F[5], c;
     if constexpr (kExact<T>) {
         const T rho = u[0];
-        const T vn = u[1] / rho, v1 = u[2] / rho, v2 = u[3] / rho;
+        const Recip64 ri = recip64(rho);
+        const T vn = div64(u[1], ri), v1 = div64(u[2], ri), v2 = div64(u[3], ri);
         const T bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
         const T vv = vn * vn + v1 * v1 + v2 * v2;
         const T p = (gamma - T(1)) * (u[4] - T(0.5) * rho * vv - T(0.5) * bb);
@@ -181,9 +241,9 @@ __device__ __forceinline__ void movers(const T* u, const T* b, T gamma, T* r, T*
         F[2] = u[2] * vn - b[0] * b[1];
         F[3] = u[3] * vn - b[0] * b[2];
         F[4] = (u[4] + ps) * vn - b[0] * bv;
-        c = fabs(vn) + sqrt(fabs(gamma * p + bb) / rho);
+        c = fabs(vn) + sqrt(div64(fabs(gamma * p + bb), ri));
     } else {
-        const T rinv = T(1) / u[0];
+        const T rinv = __builtin_amdgcn_rcpf(u[0]);
         const T vn = u[1] * rinv, v1 = u[2] * rinv, v2 = u[3] * rinv;
         const T bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
         const T ke = T(0.5) * (u[1] * vn + u[2] * v1 + u[3] * v2);
@@ -195,7 +255,7 @@ __device__ __forceinline__ void movers(const T* u, const T* b, T gamma, T* r, T*
         F[2] = u[2] * vn - b[0] * b[1];
         F[3] = u[3] * vn - b[0] * b[2];
         F[4] = (u[4] + ps) * vn - b[0] * bv;
-        c = fabs(vn) + sqrt(fabs(gamma * p + bb) * rinv);
+        c = fabs(vn) + qsqrt(fabs(gamma * p + bb) * rinv);
     }
 #pragma unroll
     for (int q = 0; q < 5; q++) {
@@ -548,10 +608,10 @@ __device__ __forceinline__ void ct_march_body(const T* __restrict__ uf, const T*
         const T bto = t0.B4, bxo = x0.B4;
         // face velocity along d on a transverse face: mass-weighted mean of the
         // two cells sharing it (Alg. 2 step 4)
-        const T Gt0 = t0.push((mTm + m0) / (rTm + r0), cur.bt, dt);
-        const T Gt1 = t1.push((m0 + mTp) / (r0 + rTp), bt1, dt);
-        const T Gx0 = x0.push((cur.mXm + m0) / (cur.rXm + r0), cur.bx0, dt);
-        const T Gx1 = x1.push((m0 + cur.mXp) / (r0 + cur.rXp), cur.bx1, dt);
+        const T Gt0 = t0.push(qdiv(mTm + m0, rTm + r0), cur.bt, dt);
+        const T Gt1 = t1.push(qdiv(m0 + mTp, r0 + rTp), bt1, dt);
+        const T Gx0 = x0.push(qdiv(cur.mXm + m0, cur.rXm + r0), cur.bx0, dt);
+        const T Gx1 = x1.push(qdiv(m0 + cur.mXp, r0 + cur.rXp), cur.bx1, dt);
         const int o = h - GB;
         if (active && o >= o0) {
             const long long co = base + (long long)o * sd;
@@ -607,14 +667,16 @@ __device__ __forceinline__ void fluid_x_body(const T* __restrict__ uin, T* __res
 {
     const int lane = threadIdx.x & 63;
     const int nx = g.n[0], ny = g.n[1];
-    const int wpr = (nx + XW - 1) / XW;   // wavefronts per row
-    const long long nrows = (long long)ny * g.n[2];
-    const long long wave = (long long)lb * 4 + (threadIdx.x >> 6);
-    const long long row = wave / wpr;
+    // wavefront-uniform indices (scalar registers); 32 bits suffice, since a
+    // grid that fits in device memory has fewer than 2^32 wavefronts
+    const unsigned wpr = (unsigned)(nx + XW - 1) / XW;   // wavefronts per row
+    const unsigned nrows = (unsigned)ny * (unsigned)g.n[2];
+    const unsigned wave = lb * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned row = wave / wpr;
     const int seg = (int)(wave - row * wpr);
     const bool live = row < nrows;        // wavefronts past the last row only join the block reduction
-    const long long rowc = live ? row : 0;
-    const int j = (int)(rowc % ny), k = (int)(rowc / ny);
+    const unsigned rowc = live ? row : 0u;
+    const int j = (int)(rowc % (unsigned)ny), k = (int)(rowc / (unsigned)ny);
     const int xu = seg * XW - GF + lane;  // position along x before the boundary map
     const int x = wrap_idx(xu, nx, g.bc), xn = wrap_idx(xu + 1, nx, g.bc);
     const long long N = g.N;
@@ -697,13 +759,13 @@ __device__ __forceinline__ void ct_x_body(const T* __restrict__ uf, const T* __r
 {
     const int lane = threadIdx.x & 63;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    const int wpr = (nx + XWC - 1) / XWC;
-    const long long nrows = (long long)ny * nz;
-    const long long wave = (long long)lb * 4 + (threadIdx.x >> 6);
-    const long long row = wave / wpr;
+    const unsigned wpr = (unsigned)(nx + XWC - 1) / XWC;
+    const unsigned nrows = (unsigned)ny * (unsigned)nz;
+    const unsigned wave = lb * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned row = wave / wpr;
     if (row >= nrows) return;   // no barrier follows: whole wavefronts past the last row leave
     const int seg = (int)(wave - row * wpr);
-    const int j = (int)(row % ny), k = (int)(row / ny);
+    const int j = (int)(row % (unsigned)ny), k = (int)(row / (unsigned)ny);
     const int xu = seg * XWC - GB + lane;
     const int x = wrap_idx(xu, nx, g.bc);
     const int jm = wrap_idx(j - 1, ny, g.bc), jp = wrap_idx(j + 1, ny, g.bc);
@@ -720,10 +782,10 @@ __device__ __forceinline__ void ct_x_body(const T* __restrict__ uf, const T* __r
     // pencil e: 0 = B_y own, 1 = B_y at +y, 2 = B_z own, 3 = B_z at +z
     T vh[4], Bk[4];
     const T r0 = uf[c], m0 = uf[N + c];
-    vh[0] = (uf[N + cym] + m0) / (uf[cym] + r0);
-    vh[1] = (m0 + uf[N + cyp]) / (r0 + uf[cyp]);
-    vh[2] = (uf[N + czm] + m0) / (uf[czm] + r0);
-    vh[3] = (m0 + uf[N + czp]) / (r0 + uf[czp]);
+    vh[0] = qdiv(uf[N + cym] + m0, uf[cym] + r0);
+    vh[1] = qdiv(m0 + uf[N + cyp], r0 + uf[cyp]);
+    vh[2] = qdiv(uf[N + czm] + m0, uf[czm] + r0);
+    vh[3] = qdiv(m0 + uf[N + czp], r0 + uf[czp]);
     Bk[0] = bin[N + c];
     Bk[1] = bin[N + cyp];
     Bk[2] = bin[2 * N + c];
