@@ -98,10 +98,10 @@ void tile_default(const Grid& g, int kind, int* p0, int* p1)
     case KIND_CFL: *p0 = reduce_blocks(g); break;
     case KIND_FLUID_X:
     case KIND_CT_X: *p0 = 0; break;   // one shape: wavefronts of 64 cells along x
-    case KIND_FLUID_Y: *p0 = march_chunk(g, 1, GF); break;
-    case KIND_FLUID_Z: *p0 = march_chunk(g, 2, GF); break;
-    case KIND_CT_Y: *p0 = march_chunk(g, 1, GB); break;
-    default: *p0 = march_chunk(g, 2, GB); break;
+    case KIND_FLUID_Y: *p0 = march_chunk(g, 1, GF, kFluidMarchWaves); break;
+    case KIND_FLUID_Z: *p0 = march_chunk(g, 2, GF, kFluidMarchWaves); break;
+    case KIND_CT_Y: *p0 = march_chunk(g, 1, GB, kCtMarchWaves<T>); break;
+    default: *p0 = march_chunk(g, 2, GB, kCtMarchWaves<T>); break;
     }
 }
 

@@ -405,6 +405,13 @@ struct EmfPipe {
 // writes (the last sweep of a step), so the next step needs no extra pass.
 constexpr int MW = 4;   // wavefronts per marching workgroup
 
+// Wavefronts per marching launch, measured best on 256^3: 2048 (chunks of 128
+// cells, half the warm-up of 64-cell chunks) except for the FP32 field sweep,
+// which at occupancy 4 needs 4096 to fill the device.
+constexpr long long kFluidMarchWaves = 2048;
+template <typename T>
+constexpr long long kCtMarchWaves = kExact<T> ? 2048 : 4096;
+
 struct MarchTile {
     int i, tc, o0, o1;
     bool active;
@@ -981,14 +988,15 @@ int reduce_blocks(const Grid& g)
     return (int)b;
 }
 
-// chunk length along the sweep for the marching kernels: enough workgroups to
-// fill the device, but long chunks to keep the warm-up share small
-int march_chunk(const Grid& g, int d, int ghost)
+// chunk length along the sweep for the marching kernels: about `target`
+// wavefronts in all (enough to fill the device), but long chunks to keep the
+// warm-up share small
+int march_chunk(const Grid& g, int d, int ghost, long long target)
 {
     const int ta = (d == 1) ? 2 : 1;
     const long long waves = ((g.n[0] + 63) / 64) * (long long)g.n[ta];
     const int nd = g.n[d];
-    long long want = 4096 / (waves > 0 ? waves : 1);
+    long long want = target / (waves > 0 ? waves : 1);
     if (want < 1) want = 1;
     int chunk = (int)((nd + want - 1) / want);
     const int minchunk = 16 * ghost;
@@ -1034,7 +1042,7 @@ static void fluid_launch(int axis, const T* u_in, T* u_out, const T* b, Grid g, 
         hipLaunchKernelGGL((fluid_x_wave<T, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
                            parts);
     } else {
-        const int chunk = march_chunk(g, axis, GF);
+        const int chunk = march_chunk(g, axis, GF, kFluidMarchWaves);
         nb = march_blocks(g, axis, chunk);
         const dim3 block(64, MW);
         if (axis == 1)
@@ -1065,7 +1073,7 @@ hipError_t launch_ct(int axis, const T* u, const T* b_in, T* b_out, Grid g, cons
     if (axis == 0) {
         hipLaunchKernelGGL((ct_x_wave<T>), dim3(ct_x_wave_blocks(g)), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt);
     } else {
-        const int chunk = march_chunk(g, axis, GB);
+        const int chunk = march_chunk(g, axis, GB, kCtMarchWaves<T>);
         const dim3 grid(march_blocks(g, axis, chunk)), block(64, MW);
         if (axis == 1)
             hipLaunchKernelGGL((ct_march<T, 1>), grid, block, 0, s, u, b_in, b_out, g, ctl, dt, chunk);
