@@ -215,9 +215,6 @@ class _Producer:
             self.window.append(self.pool.submit(self.make, self.specs[self.k]))
             self.k += 1
 
-    def ready(self):
-        return bool(self.window) and self.window[0].done()
-
     def next(self):
         st = self.window.popleft().result()
         self._push()
@@ -232,15 +229,23 @@ def _pct(xs, q):
     return round(float(np.percentile(np.asarray(xs), q)), 4)
 
 
-def serve_once(B, P, specs, arrivals, budget):
-    """Open-loop run: request i arrives at arrivals[i] seconds after the start; returns
-    (latencies, makespan, late submissions)."""
-    n = len(specs)
+def build_states(P, specs):
+    """Every request's initial state, built on a few host threads before any timed run (a request
+    arrives with its state)."""
     prod = _Producer(P, specs)
+    return [prod.next() for _ in specs]
+
+
+def serve_once(B, P, specs, arrivals, budget, max_cells=None, states=None):
+    """Open-loop run: request i arrives, with its state already built, at arrivals[i] seconds after
+    the start; returns (latencies, makespan, late submissions)."""
+    n = len(specs)
+    if states is None:
+        states = build_states(P, specs)
     lat = [0.0] * n
     idx = {}
     late = 0
-    with B.Server(budget) as srv:
+    with B.Server(budget, max_cells=max_cells) as srv:
         t0 = B.mhd_server_now()
         nxt = done = 0
         running = queued = 0
@@ -248,10 +253,8 @@ def serve_once(B, P, specs, arrivals, budget):
         while done < n:
             now = B.mhd_server_now() - t0
             while nxt < n and arrivals[nxt] <= now:
-                if not prod.ready() and (running or queued):
-                    break      # keep the device busy; submit when the state is built
                 sp = specs[nxt]
-                st = prod.next()
+                st = states[nxt]
                 if B.mhd_server_now() - t0 > arrivals[nxt] + 0.05:
                     late += 1
                 rid = srv.submit(st, sp["gamma"], B.MHD_BC_PERIODIC, sp["dtype"], sp["nsteps"])
@@ -293,18 +296,17 @@ def _scratch(sp):
     return _scratch_bufs[key]
 
 
-def run_serving(B, P, count, fracs, budget, steps):
+def run_serving(B, P, count, fracs, budget, steps, max_cells=None):
     import numpy as np
     import torch
 
     specs = P.serving_specs(count, nsteps=steps)
     work = [sp["n"] ** 3 * sp["nsteps"] for sp in specs]
+    states = build_states(P, specs)
     # plain solves one at a time: the service time of each request alone, as a serial server would
     # spend it (create, copy in, step, copy out, release), and its stepping part
-    prod = _Producer(P, specs)
     service, stepping = [], []
-    for sp in specs:
-        st = prod.next()
+    for sp, st in zip(specs, states):
         n = sp["n"]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -318,7 +320,7 @@ def run_serving(B, P, count, fracs, budget, steps):
     print("bench: serving, plain solves %.2f s (stepping %.2f s)" % (sum(service), sum(stepping)), file=sys.stderr,
           flush=True)
     # saturation: every request present at the start
-    lat0, span0, _ = serve_once(B, P, specs, [0.0] * count, budget)
+    lat0, span0, _ = serve_once(B, P, specs, [0.0] * count, budget, max_cells, states)
     sat = count / span0
     print("bench: serving, saturation %.2f requests/s" % sat, file=sys.stderr, flush=True)
     rng = np.random.Generator(np.random.PCG64(P.MASTER_SEED + 501))
@@ -327,7 +329,7 @@ def run_serving(B, P, count, fracs, budget, steps):
     for f in fracs:
         lam = f * sat
         arr = list(np.cumsum(gaps / lam) - gaps[0] / lam)
-        lat, span, late = serve_once(B, P, specs, arr, budget)
+        lat, span, late = serve_once(B, P, specs, arr, budget, max_cells, states)
         # the same arrivals served first come, first served by plain solves
         fin, slat = 0.0, []
         for a, sv in zip(arr, service):
@@ -343,6 +345,7 @@ def run_serving(B, P, count, fracs, budget, steps):
                     "Poisson arrivals" % (count, steps),
         "requests": count,
         "hbm_budget_bytes": budget,
+        "max_running_cells": max_cells if max_cells is not None else 1 << 24,
         "cell_updates": sum(work),
         "saturation_rps": round(sat, 3),
         "saturation_cell_updates_per_s": round(sum(work) / span0, 1),
@@ -445,6 +448,8 @@ def main():
     ap.add_argument("--serve-rates", default="0.5,1.0", help="arrival rates as fractions of saturation")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--serve-steps", type=int, default=100)
+    ap.add_argument("--serve-max-cells", type=int, default=None,
+                    help="server admission cap on running cells (default: the library's, 2^24; 0: none)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM counters)")
     args = ap.parse_args()
@@ -518,7 +523,7 @@ def main():
     if not args.no_serve:
         print("bench: serving workload", file=sys.stderr, flush=True)
         out["serving"] = run_serving(B, P, args.serve_count, [float(x) for x in args.serve_rates.split(",")],
-                                     int(args.serve_budget_gb * (1 << 30)), args.serve_steps)
+                                     int(args.serve_budget_gb * (1 << 30)), args.serve_steps, args.serve_max_cells)
     if rank == 0 and not args.no_cpu_baseline:
         print("bench: cpu oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(P, n, args.cpu_sample)

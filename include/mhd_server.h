@@ -4,9 +4,9 @@
  * A request is one initial-value problem (grid, gamma, boundary condition,
  * dtype, initial state as in mhd.h) and a number of full steps. Requests
  * queue on submission and are admitted first-come first-served while their
- * device footprint (mhd_batch_problem_bytes) fits the server's HBM budget;
- * an admitted request's state stays resident on the device until it
- * finishes. Each tick advances every admitted request by one full step: FP32
+ * device footprint (mhd_batch_problem_bytes) fits the server's HBM budget
+ * and their cells fit the cell cap (mhd_server_set_max_cells); an admitted
+ * request's state stays resident on the device until it finishes. Each tick advances every admitted request by one full step: FP32
  * and FP64 requests run as two batches (include/mhd_batch.h) on two streams,
  * so their work overlaps, and requests admitted at different ticks share the
  * batched launches of their sweep order. Initial and final states move
@@ -42,6 +42,14 @@ double mhd_server_now(void);
  * (0 < cfl <= 1). */
 int mhd_server_create(size_t hbm_budget, double cfl, mhd_server_t** out);
 
+/* Admission cap on the total cells (nx * ny * nz) of the admitted requests:
+ * the head of the queue waits while admitting it would exceed `cells`, unless
+ * no request is running (so a larger one still runs, alone). 0 removes the
+ * cap; negative values are MHD_ERR_ARG. Default 2^24 (one 256^3 grid), which
+ * keeps the device busy: every admitted request shares each tick with all
+ * the others, so a larger running set only lengthens each one's latency. */
+int mhd_server_set_max_cells(mhd_server_t* s, int64_t cells);
+
 /* Release the server, its batches and every request (null is accepted). */
 int mhd_server_destroy(mhd_server_t* s);
 
@@ -55,9 +63,10 @@ int mhd_server_submit(mhd_server_t* s, int nx, int ny, int nz, double gamma, int
 /* One scheduling round: finish requests whose final state has reached the
  * host, send requests that have taken all their steps out of their batch
  * (their state follows asynchronously), admit queued requests in arrival
- * order while they fit the budget, then issue one full step of every
- * admitted request (asynchronous; the host stays at most two rounds ahead of
- * the device). A round with nothing to step waits for the oldest pending
+ * order while they fit the budget and the cell cap, then issue one full step
+ * of every admitted request (asynchronous; the host stays at most three
+ * rounds ahead of the device). A round with nothing to step waits for the
+ * oldest pending
  * copy-out. *running (admitted, including those whose state is on its way
  * out) and *queued (optional) receive the counts after the round. */
 int mhd_server_tick(mhd_server_t* s, int* running, int* queued);

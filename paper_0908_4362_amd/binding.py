@@ -89,6 +89,7 @@ def lib():
             "mhd_server_now": ([], d),
             "mhd_server_create": ([ctypes.c_size_t, d, ctypes.POINTER(vp)], i),
             "mhd_server_destroy": ([vp], i),
+            "mhd_server_set_max_cells": ([vp, ctypes.c_int64], i),
             "mhd_server_submit": ([vp, i, i, i, d, i, i, vp, i, ctypes.POINTER(i)], i),
             "mhd_server_tick": ([vp, ctypes.POINTER(i), ctypes.POINTER(i)], i),
             "mhd_server_poll": ([vp, ctypes.POINTER(i)], i),
@@ -367,6 +368,10 @@ def mhd_server_destroy(s):
     _check(lib().mhd_server_destroy(s))
 
 
+def mhd_server_set_max_cells(s, cells: int):
+    _check(lib().mhd_server_set_max_cells(s, int(cells)))
+
+
 def mhd_server_submit(s, nx: int, ny: int, nz: int, gamma: float, bc: int, dtype: int, host_state: np.ndarray,
                       nsteps: int) -> int:
     a = np.ascontiguousarray(host_state, dtype=_np_dtype(dtype))
@@ -416,9 +421,11 @@ def mhd_server_stats(s):
 class Server:
     """Owning wrapper of one request server (host-side convenience; no computation)."""
 
-    def __init__(self, hbm_budget: int, cfl: float = 0.7):
+    def __init__(self, hbm_budget: int, cfl: float = 0.7, max_cells=None):
         self.s = mhd_server_create(hbm_budget, cfl)
         self.meta = {}
+        if max_cells is not None:
+            mhd_server_set_max_cells(self.s, max_cells)
 
     def close(self):
         if self.s is not None:

@@ -32,6 +32,10 @@ namespace {
 constexpr int kAhead = 3;
 constexpr size_t kStageLimit = (size_t)2 << 30;   // pinned bytes staged ahead of admission
 constexpr int kDraining = 3;   // phase between leaving the batch and the copy-out completing
+// Admission cap on the cells of the running requests: one 256^3 grid keeps
+// the device busy; admitting more only makes every running request share the
+// device with more others, which lengthens each one's latency.
+constexpr long long kDefaultMaxCells = 1LL << 24;
 
 struct Req {
     int nx, ny, nz, bc, dtype, nsteps;
@@ -68,6 +72,7 @@ int hip_fail(hipError_t e, const char* where) { return mhd::report_hip(e, where)
 struct mhd_server {
     size_t budget;
     size_t used;                 // device blocks of running and draining requests
+    long long max_cells;         // admission cap on the cells of running requests (0: none)
     double cfl;
     int device;
     mhd_batch_t* batch[2];       // indexed by dtype
@@ -319,6 +324,7 @@ int mhd_server_create(size_t hbm_budget, double cfl, mhd_server_t** out)
     if (!s) return fail(MHD_ERR_OOM, "host allocation failed");
     s->budget = hbm_budget;
     s->used = 0;
+    s->max_cells = kDefaultMaxCells;
     s->cfl = cfl;
     s->next_id = 1;
     s->cell_updates = 0;
@@ -382,6 +388,14 @@ int mhd_server_destroy(mhd_server_t* s)
             if (s->pace[k][d]) (void)hipEventDestroy(s->pace[k][d]);
     if (s->copy) (void)hipStreamDestroy(s->copy);
     delete s;
+    return MHD_OK;
+}
+
+int mhd_server_set_max_cells(mhd_server_t* s, int64_t cells)
+{
+    if (!s) return fail(MHD_ERR_ARG, "null server");
+    if (cells < 0) return fail(MHD_ERR_ARG, "cell cap must be >= 0");
+    s->max_cells = (long long)cells;
     return MHD_OK;
 }
 
@@ -452,10 +466,18 @@ int mhd_server_tick(mhd_server_t* s, int* running, int* queued)
     }
     s->running.swap(keep);
     // 3. admit in arrival order while the head of the queue fits the budget
+    //    and the cell cap (a request is always admitted when none runs)
+    long long cells = 0;
+    for (int id : s->running) {
+        const Req& r = s->reqs.at(id);
+        cells += (long long)r.nx * r.ny * r.nz;
+    }
     while (!s->queue.empty()) {
         const int id = s->queue.front();
         Req& head = s->reqs.at(id);
         if (s->used + head.bytes > s->budget) break;
+        const long long head_cells = (long long)head.nx * head.ny * head.nz;
+        if (s->max_cells > 0 && !s->running.empty() && cells + head_cells > s->max_cells) break;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             if (!head.staged) {
@@ -472,7 +494,10 @@ int mhd_server_tick(mhd_server_t* s, int* running, int* queued)
         const int rc = admit(s, id, &room);
         if (rc == MHD_OK && !room) break;
         s->queue.pop_front();
-        if (rc != MHD_OK) fail_request(s, id, rc);
+        if (rc != MHD_OK)
+            fail_request(s, id, rc);
+        else
+            cells += head_cells;
     }
     // 4. one full step of every admitted request; the two batches run on
     //    their own streams and overlap

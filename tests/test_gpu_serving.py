@@ -123,3 +123,33 @@ def test_failed_request_does_not_disturb_the_others(B):
         assert np.array_equal(done[rz][1], stall.astype(np.float32))
         assert done[rg][0]["status"] == B.MHD_OK
         assert np.array_equal(done[rg][1], alone(B, good, 5.0 / 3.0, 0, B.MHD_F64, 6)[0])
+
+
+def test_cell_cap_admits_one_request_at_a_time(B):
+    """With a cell cap of 1 a request is admitted only when no other is
+    stepping (one still runs when nothing else does); results are unchanged."""
+    reqs = small_requests()[:5]
+    note("serving with a cell cap of 1")
+    with B.Server(1 << 30, max_cells=1) as srv:
+        with pytest.raises(B.MHDError) as ei:
+            B.mhd_server_set_max_cells(srv.s, -1)
+        assert ei.value.code == B.MHD_ERR_ARG
+        ids = {srv.submit(st, gm, bc, dt, ns): k for k, (st, gm, bc, dt, ns) in enumerate(reqs)}
+        results = {}
+        ticks = 0
+        while len(results) < len(reqs):
+            srv.tick()
+            ticks += 1
+            stepping = 0
+            for rid, k in ids.items():
+                if k in results:
+                    continue
+                info = srv.info(rid)
+                if info["state"] == B.MHD_REQ_RUNNING and info["steps"] < reqs[k][4]:
+                    stepping += 1
+            assert stepping <= 1
+            for rid in srv.finished():
+                results[ids[rid]] = srv.take(rid)
+            assert ticks < 1000
+    for k, (st, gm, bc, dt, ns) in enumerate(reqs):
+        assert np.array_equal(results[k], alone(B, st, gm, bc, dt, ns)[0]), k

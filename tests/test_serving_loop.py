@@ -17,8 +17,9 @@ from paper_0908_4362_amd import problems as P
 
 
 class ModelServer:
-    def __init__(self, budget, cfl=0.7):
+    def __init__(self, budget, cfl=0.7, max_cells=None):
         self.budget, self.used = budget, 0
+        self.max_cells = (1 << 24) if max_cells is None else max_cells
         self.reqs, self.queue, self.running, self.done = {}, collections.deque(), [], collections.deque()
         self.next_id, self.meta, self.s, self.ticks, self.peak = 1, {}, self, 0, 0
 
@@ -34,7 +35,7 @@ class ModelServer:
         assert b <= self.budget
         rid = self.next_id
         self.next_id += 1
-        self.reqs[rid] = {"bytes": b, "nsteps": nsteps, "issued": 0, "t_submit": time.monotonic(), "t_admit": -1.0,
+        self.reqs[rid] = {"bytes": b, "cells": n ** 3, "nsteps": nsteps, "issued": 0, "t_submit": time.monotonic(), "t_admit": -1.0,
                           "t_finish": -1.0, "status": 0}
         self.queue.append(rid)
         self.meta[rid] = (st.shape, dtype)
@@ -52,10 +53,14 @@ class ModelServer:
             else:
                 keep.append(rid)
         self.running = keep
+        cells = sum(self.reqs[rid]["cells"] for rid in self.running)
         while self.queue:
             r = self.reqs[self.queue[0]]
             if self.used + r["bytes"] > self.budget:
                 break
+            if self.max_cells and self.running and cells + r["cells"] > self.max_cells:
+                break
+            cells += r["cells"]
             self.used += r["bytes"]
             r["t_admit"] = time.monotonic()
             self.running.append(self.queue.popleft())
@@ -74,8 +79,8 @@ class ModelServer:
 
 
 def model_binding(servers):
-    def make(budget, cfl=0.7):
-        s = ModelServer(budget, cfl)
+    def make(budget, cfl=0.7, max_cells=None):
+        s = ModelServer(budget, cfl, max_cells)
         servers.append(s)
         return s
 
@@ -99,3 +104,16 @@ def test_spread_arrivals_are_all_served():
     lat, span, late = bench.serve_once(model_binding(servers), P, specs, arr, 1 << 30)
     assert min(lat) >= 0.0 and span >= arr[-1]
     assert not servers[0].reqs
+
+
+def test_burst_under_a_cell_cap_is_served_in_order():
+    """The bench loop with the server's admission cell cap: every request is
+    served even when the cap holds the queue back, including a cap below a
+    single request (it then runs alone)."""
+    for cap in (1, 2 * 12 ** 3, 0):
+        servers = []
+        specs = P.serving_specs(12, nsteps=3, sizes=(8, 12, 16))
+        lat, span, late = bench.serve_once(model_binding(servers), P, specs, [0.0] * len(specs), 1 << 30,
+                                           max_cells=cap)
+        assert len(lat) == len(specs) and min(lat) >= 0.0
+        assert not servers[0].reqs and servers[0].max_cells == cap
