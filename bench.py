@@ -257,7 +257,8 @@ def serve_once(B, P, specs, arrivals, budget, max_cells=None, states=None):
                 st = states[nxt]
                 if B.mhd_server_now() - t0 > arrivals[nxt] + 0.05:
                     late += 1
-                rid = srv.submit(st, sp["gamma"], B.MHD_BC_PERIODIC, sp["dtype"], sp["nsteps"])
+                # lent, not copied: the state stays alive in `states` for the whole run
+                rid = srv.submit(st, sp["gamma"], B.MHD_BC_PERIODIC, sp["dtype"], sp["nsteps"], lend=True)
                 idx[rid] = nxt
                 nxt += 1
                 now = B.mhd_server_now() - t0

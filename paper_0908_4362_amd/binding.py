@@ -91,6 +91,7 @@ def lib():
             "mhd_server_destroy": ([vp], i),
             "mhd_server_set_max_cells": ([vp, ctypes.c_int64], i),
             "mhd_server_submit": ([vp, i, i, i, d, i, i, vp, i, ctypes.POINTER(i)], i),
+            "mhd_server_submit_ref": ([vp, i, i, i, d, i, i, vp, i, ctypes.POINTER(i)], i),
             "mhd_server_tick": ([vp, ctypes.POINTER(i), ctypes.POINTER(i)], i),
             "mhd_server_poll": ([vp, ctypes.POINTER(i)], i),
             "mhd_server_info": ([vp, i, ctypes.POINTER(i), ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64),
@@ -381,6 +382,19 @@ def mhd_server_submit(s, nx: int, ny: int, nz: int, gamma: float, bc: int, dtype
     return rid.value
 
 
+def mhd_server_submit_ref(s, nx: int, ny: int, nz: int, gamma: float, bc: int, dtype: int, host_state: np.ndarray,
+                          nsteps: int) -> int:
+    """Lend host_state (C-contiguous, of the request's dtype, no temporary copy is made) until the request
+    leaves the queue; the caller keeps it alive and unchanged until then."""
+    if not (isinstance(host_state, np.ndarray) and host_state.flags.c_contiguous
+            and host_state.dtype == _np_dtype(dtype)):
+        raise ValueError("a lent state must be a C-contiguous array of the request's dtype")
+    rid = ctypes.c_int()
+    _check(lib().mhd_server_submit_ref(s, nx, ny, nz, gamma, bc, dtype, host_state.ctypes.data_as(ctypes.c_void_p),
+                                       nsteps, ctypes.byref(rid)))
+    return rid.value
+
+
 def mhd_server_tick(s):
     running = ctypes.c_int()
     queued = ctypes.c_int()
@@ -424,6 +438,7 @@ class Server:
     def __init__(self, hbm_budget: int, cfl: float = 0.7, max_cells=None):
         self.s = mhd_server_create(hbm_budget, cfl)
         self.meta = {}
+        self.lent = {}   # request id -> lent state, held until the request is taken
         if max_cells is not None:
             mhd_server_set_max_cells(self.s, max_cells)
 
@@ -431,6 +446,7 @@ class Server:
         if self.s is not None:
             mhd_server_destroy(self.s)
             self.s = None
+        self.lent.clear()
 
     def __enter__(self):
         return self
@@ -444,9 +460,13 @@ class Server:
         except Exception:
             pass
 
-    def submit(self, state: np.ndarray, gamma: float, bc: int, dtype: int, nsteps: int) -> int:
+    def submit(self, state: np.ndarray, gamma: float, bc: int, dtype: int, nsteps: int, lend: bool = False) -> int:
         nz, ny, nx = state.shape[1:]
-        rid = mhd_server_submit(self.s, nx, ny, nz, gamma, bc, dtype, state, nsteps)
+        if lend:
+            rid = mhd_server_submit_ref(self.s, nx, ny, nz, gamma, bc, dtype, state, nsteps)
+            self.lent[rid] = state
+        else:
+            rid = mhd_server_submit(self.s, nx, ny, nz, gamma, bc, dtype, state, nsteps)
         self.meta[rid] = (state.shape, dtype)
         return rid
 
@@ -468,7 +488,9 @@ class Server:
     def take(self, rid: int) -> np.ndarray:
         shape, dtype = self.meta.pop(rid)
         out = np.empty(shape, dtype=_np_dtype(dtype))
-        return mhd_server_take(self.s, rid, out)
+        mhd_server_take(self.s, rid, out)
+        self.lent.pop(rid, None)
+        return out
 
 
 class Batch:

@@ -43,6 +43,7 @@ struct Req {
     size_t bytes = 0;            // device block
     size_t sbytes = 0;           // state: 8 fields
     std::vector<char> input;     // pageable copy of the initial state until admission
+    const void* ext = nullptr;   // or the caller's buffer, lent until the request leaves the queue
     void* host = nullptr;        // pinned: staged input, then final state + control block
     bool staged = false;         // host holds the input
     bool counted = false;        // host counts in staged_bytes (staged, not yet admitted)
@@ -177,8 +178,9 @@ void stage_loop(mhd_server* s)
             rc = MHD_ERR_OOM;
         }
         if (buf) {
-            std::memcpy(buf, r.input.data(), r.sbytes);
+            std::memcpy(buf, r.ext ? r.ext : static_cast<const void*>(r.input.data()), r.sbytes);
             std::vector<char>().swap(r.input);
+            r.ext = nullptr;
         }
         lk.lock();
         r.host = buf;
@@ -298,10 +300,67 @@ int poll_draining(mhd_server* s)
 void fail_request(mhd_server* s, int id, int status)
 {
     Req& r = s->reqs.at(id);
+    if (r.ext) {
+        // the caller's buffer is still lent (the request was queued): keep a
+        // copy of the input, which mhd_server_take returns for a request never run
+        try {
+            const char* p = static_cast<const char*>(r.ext);
+            r.input.assign(p, p + r.sbytes);
+        } catch (...) {
+        }
+        r.ext = nullptr;
+    }
     r.status = status;
     r.phase = MHD_REQ_DONE;
     r.t_finish = mhd_server_now();
     s->done.push_back(id);
+}
+
+// Queue a request (checks as mhd_server_submit); with `lend` the caller's
+// buffer is read in place by the staging thread instead of copied here.
+int submit(mhd_server* s, int nx, int ny, int nz, double gamma, int bc, int dtype, const void* host_state,
+           int nsteps, bool lend, int* req)
+{
+    if (!s) return fail(MHD_ERR_ARG, "null server");
+    if (!req || !host_state) return fail(MHD_ERR_ARG, "null pointer");
+    if (dtype != MHD_F32 && dtype != MHD_F64) return fail(MHD_ERR_ARG, "unknown dtype");
+    if (nsteps < 1) return fail(MHD_ERR_ARG, "nsteps must be >= 1");
+    if (!(gamma > 1.0) || (bc != MHD_BC_PERIODIC && bc != MHD_BC_OUTFLOW))
+        return fail(MHD_ERR_ARG, "invalid gamma or boundary condition");
+    const size_t bytes = mhd_batch_problem_bytes(nx, ny, nz, dtype);
+    if (bytes == 0) return fail(MHD_ERR_ARG, "invalid grid");
+    if (bytes > s->budget) return fail(MHD_ERR_ARG, "request larger than the server's HBM budget");
+    Req r;
+    r.nx = nx;
+    r.ny = ny;
+    r.nz = nz;
+    r.bc = bc;
+    r.dtype = dtype;
+    r.nsteps = nsteps;
+    r.gamma = gamma;
+    r.bytes = bytes;
+    r.sbytes = 8 * (size_t)nx * ny * nz * (dtype == MHD_F64 ? 8 : 4);
+    if (lend) {
+        r.ext = host_state;
+    } else {
+        try {
+            r.input.resize(r.sbytes);
+        } catch (...) {
+            return fail(MHD_ERR_OOM, "host allocation failed");
+        }
+        std::memcpy(r.input.data(), host_state, r.sbytes);
+    }
+    r.t_submit = mhd_server_now();
+    const int id = s->next_id++;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->reqs.emplace(id, std::move(r));
+        s->stage_queue.push_back(id);
+    }
+    s->work_cv.notify_one();
+    s->queue.push_back(id);
+    *req = id;
+    return MHD_OK;
 }
 
 }  // namespace
@@ -402,42 +461,13 @@ int mhd_server_set_max_cells(mhd_server_t* s, int64_t cells)
 int mhd_server_submit(mhd_server_t* s, int nx, int ny, int nz, double gamma, int bc, int dtype,
                       const void* host_state, int nsteps, int* req)
 {
-    if (!s) return fail(MHD_ERR_ARG, "null server");
-    if (!req || !host_state) return fail(MHD_ERR_ARG, "null pointer");
-    if (dtype != MHD_F32 && dtype != MHD_F64) return fail(MHD_ERR_ARG, "unknown dtype");
-    if (nsteps < 1) return fail(MHD_ERR_ARG, "nsteps must be >= 1");
-    if (!(gamma > 1.0) || (bc != MHD_BC_PERIODIC && bc != MHD_BC_OUTFLOW))
-        return fail(MHD_ERR_ARG, "invalid gamma or boundary condition");
-    const size_t bytes = mhd_batch_problem_bytes(nx, ny, nz, dtype);
-    if (bytes == 0) return fail(MHD_ERR_ARG, "invalid grid");
-    if (bytes > s->budget) return fail(MHD_ERR_ARG, "request larger than the server's HBM budget");
-    Req r;
-    r.nx = nx;
-    r.ny = ny;
-    r.nz = nz;
-    r.bc = bc;
-    r.dtype = dtype;
-    r.nsteps = nsteps;
-    r.gamma = gamma;
-    r.bytes = bytes;
-    r.sbytes = 8 * (size_t)nx * ny * nz * (dtype == MHD_F64 ? 8 : 4);
-    try {
-        r.input.resize(r.sbytes);
-    } catch (...) {
-        return fail(MHD_ERR_OOM, "host allocation failed");
-    }
-    std::memcpy(r.input.data(), host_state, r.sbytes);
-    r.t_submit = mhd_server_now();
-    const int id = s->next_id++;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->reqs.emplace(id, std::move(r));
-        s->stage_queue.push_back(id);
-    }
-    s->work_cv.notify_one();
-    s->queue.push_back(id);
-    *req = id;
-    return MHD_OK;
+    return submit(s, nx, ny, nz, gamma, bc, dtype, host_state, nsteps, false, req);
+}
+
+int mhd_server_submit_ref(mhd_server_t* s, int nx, int ny, int nz, double gamma, int bc, int dtype,
+                          const void* host_state, int nsteps, int* req)
+{
+    return submit(s, nx, ny, nz, gamma, bc, dtype, host_state, nsteps, true, req);
 }
 
 int mhd_server_tick(mhd_server_t* s, int* running, int* queued)

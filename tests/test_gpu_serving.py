@@ -153,3 +153,34 @@ def test_cell_cap_admits_one_request_at_a_time(B):
             assert ticks < 1000
     for k, (st, gm, bc, dt, ns) in enumerate(reqs):
         assert np.array_equal(results[k], alone(B, st, gm, bc, dt, ns)[0]), k
+
+
+def test_lent_states_give_the_same_results(B):
+    """Requests submitted with their state lent (read in place by the staging
+    thread) are served exactly as copied ones; a lent state that the device
+    check rejects fails alone, and its request returns the input."""
+    reqs = small_requests()[:4]
+    bad = P.random_smooth(14, 12, 10, seed=P.MASTER_SEED + 620)
+    bad[0, 1, 2, 3] = -1.0               # non-positive density: rejected
+    note("serving lent states")
+    with B.Server(1 << 30) as srv:
+        ids = {}
+        for k, (st, gm, bc, dt, ns) in enumerate(reqs):
+            ids[srv.submit(np.ascontiguousarray(st), gm, bc, dt, ns, lend=True)] = k
+        rb = srv.submit(bad, 5.0 / 3.0, 0, B.MHD_F64, 3, lend=True)
+        results, failed = {}, None
+        for _ in range(200):
+            srv.tick()
+            for rid in srv.finished():
+                info = srv.info(rid)
+                if rid == rb:
+                    failed = (info, srv.take(rid))
+                else:
+                    assert info["status"] == B.MHD_OK
+                    results[ids[rid]] = srv.take(rid)
+            if len(results) == len(reqs) and failed is not None:
+                break
+    assert failed is not None and failed[0]["status"] == B.MHD_ERR_ARG
+    assert np.array_equal(failed[1], bad)
+    for k, (st, gm, bc, dt, ns) in enumerate(reqs):
+        assert np.array_equal(results[k], alone(B, st, gm, bc, dt, ns)[0]), k

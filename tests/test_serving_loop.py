@@ -29,7 +29,7 @@ class ModelServer:
     def __exit__(self, *exc):
         pass
 
-    def submit(self, st, gamma, bc, dtype, nsteps):
+    def submit(self, st, gamma, bc, dtype, nsteps, lend=False):
         n = st.shape[1]
         b = 16 * n ** 3 * (8 if dtype else 4)
         assert b <= self.budget
