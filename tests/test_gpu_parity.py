@@ -295,3 +295,22 @@ def test_fp64_path_reproduces_oracle_bitwise(B, orc, case):
     assert t == tw
     bad = [f for f in range(8) if not np.array_equal(got[f], want[f])]
     assert not bad, (bad, field_errors(got, want))
+
+
+@pytest.mark.parametrize("alpha", [1e-90, 1e90])
+def test_fp64_bitwise_on_scaled_states(B, orc, alpha):
+    """rho, m, E scaled by alpha and B by sqrt(alpha) (the same flow: velocities
+    and wave speeds, hence dt, are unchanged) move every quotient of the step
+    -- v = m / rho, the face velocities, the limiter's ab / (a + b) -- ninety
+    decades up or down; the FP64 path must still reproduce the oracle bit for
+    bit, which pins its division sequence well away from unit scale."""
+    s = P.random_smooth(29, 23, 19, seed=P.MASTER_SEED + 52).copy()
+    s[:5] *= alpha
+    s[5:] *= np.sqrt(alpha)
+    g = orc.Grid(29, 23, 19, H.GAMMA53, 0)
+    note("bitwise scaled state %g" % alpha)
+    got, (t, _) = gpu_run(B, s, H.GAMMA53, 0, B.MHD_F64, 6)
+    want, tw, _ = orc.run(g, s, 6, 0.7)
+    assert t == tw
+    bad = [f for f in range(8) if not np.array_equal(got[f], want[f])]
+    assert not bad, (bad, field_errors(got, want))
