@@ -138,9 +138,10 @@ unsigned tile_blocks(const Grid& g, int kind, int p0, int p1)
     case KIND_CFL: return (unsigned)p0;
     case KIND_FLUID_X: return x_wave_blocks(g);
     case KIND_CT_X: return ct_x_wave_blocks(g);
-    case KIND_FLUID_Y:
-    case KIND_CT_Y: return march_blocks(g, 1, p0);
-    default: return march_blocks(g, 2, p0);
+    case KIND_FLUID_Y: return march_blocks(g, 1, p0, kMarchXWide<T, false>);
+    case KIND_CT_Y: return march_blocks(g, 1, p0, kMarchXWide<T, true>);
+    case KIND_FLUID_Z: return march_blocks(g, 2, p0, kMarchXWide<T, false>);
+    default: return march_blocks(g, 2, p0, kMarchXWide<T, true>);
     }
 }
 
