@@ -64,7 +64,6 @@ struct Cohort {
     BJob* jobs = nullptr;
     TileDesc* td[mhd::KIND_COUNT] = {};
     unsigned nblocks[mhd::KIND_COUNT] = {};
-    size_t lds[mhd::KIND_COUNT] = {};
     hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
     double exec_cfl[3] = {0.0, 0.0, 0.0};
 };
@@ -252,7 +251,6 @@ int build_tables(mhd_batch* b, Cohort& c)
     std::vector<TileDesc> td[mhd::KIND_COUNT];
     for (int k = 0; k < mhd::KIND_COUNT; k++) {
         td[k].resize(n + 1);
-        c.lds[k] = 0;
     }
     for (int j = 0; j < n; j++) {
         const Prob& p = b->probs.at(c.ids[j]);
@@ -274,12 +272,10 @@ int build_tables(mhd_batch* b, Cohort& c)
             tile_of_dyn(b, g, k, &p0, &p1);
             const unsigned nb = b->dtype == MHD_F64 ? mhd::tile_blocks<double>(g, k, p0, p1)
                                                     : mhd::tile_blocks<float>(g, k, p0, p1);
-            const size_t lds = b->dtype == MHD_F64 ? mhd::tile_lds<double>(k, p0, p1) : mhd::tile_lds<float>(k, p0, p1);
             td[k][j].first = first;
             td[k][j].p0 = p0;
             td[k][j].p1 = p1;
             td[k][j].pad = 0;
-            c.lds[k] = std::max(c.lds[k], lds);
             if ((unsigned long long)first + nb > 0x7fffffffULL) return fail(MHD_ERR_ARG, "batch launch too large");
             first += nb;
         }
@@ -321,7 +317,7 @@ template <typename T>
 int launch_kind(mhd_batch* b, Cohort& c, int kind, bool cfl_parts, int iu, int ib)
 {
     const int n = (int)c.ids.size();
-    HIPCHK(mhd::launch_batch<T>(kind, cfl_parts, c.jobs, c.td[kind], n, c.nblocks[kind], c.lds[kind], iu, ib,
+    HIPCHK(mhd::launch_batch<T>(kind, cfl_parts, c.jobs, c.td[kind], n, c.nblocks[kind], iu, ib,
                                 b->stream),
            "batched launch");
     return MHD_OK;

@@ -146,14 +146,8 @@ unsigned tile_blocks(const Grid& g, int kind, int p0, int p1)
 }
 
 template <typename T>
-size_t tile_lds(int, int, int)
-{
-    return 0;   // no kernel of the step uses dynamic LDS
-}
-
-template <typename T>
 hipError_t launch_batch(int kind, bool cfl_parts, const BJob* jobs, const TileDesc* td, int njobs, unsigned nb,
-                        size_t lds, int iu, int ib, hipStream_t s)
+                        int iu, int ib, hipStream_t s)
 {
     if (nb == 0 || njobs == 0) return hipSuccess;
     const dim3 mblock(64, MW);

@@ -86,15 +86,13 @@ struct TileDesc {
 };
 
 // Tiles of one kind for a problem: the plain solver's choice, the
-// candidates the autotuner may time, workgroup count and LDS bytes.
+// candidates the autotuner may time, and the workgroup count.
 template <typename T>
 void tile_default(const Grid& g, int kind, int* p0, int* p1);
 template <typename T>
 void tile_candidates(const Grid& g, int kind, std::vector<std::pair<int, int>>& out);
 template <typename T>
 unsigned tile_blocks(const Grid& g, int kind, int p0, int p1);
-template <typename T>
-size_t tile_lds(int kind, int p0, int p1);
 
 // One batched sub-operation over njobs problems (tables in device memory,
 // nblocks = last first + last count). iu / ib select the ping-pong copies
@@ -102,7 +100,7 @@ size_t tile_lds(int kind, int p0, int p1);
 // per-workgroup CFL maxima into each problem's parts.
 template <typename T>
 hipError_t launch_batch(int kind, bool cfl_parts, const BJob* jobs, const TileDesc* td, int njobs, unsigned nblocks,
-                        size_t lds, int iu, int ib, hipStream_t s);
+                        int iu, int ib, hipStream_t s);
 // Per-problem second level of the c_max reduction (td: the producing launch's
 // table) and the dt rule of each problem.
 hipError_t launch_finish_batch(const BJob* jobs, const TileDesc* td, int njobs, double cfl, hipStream_t s);
