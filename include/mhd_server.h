@@ -63,8 +63,9 @@ int mhd_server_submit(mhd_server_t* s, int nx, int ny, int nz, double gamma, int
 /* As mhd_server_submit, but the initial state is read from the caller's
  * buffer in place rather than copied at submission: the buffer is lent until
  * the request leaves the queue (mhd_server_info reports a state other than
- * MHD_REQ_QUEUED) and must stay valid and unchanged until then. This saves
- * one host copy of the state. */
+ * MHD_REQ_QUEUED) or mhd_server_destroy returns, whichever comes first, and
+ * must stay valid and unchanged until then. This saves one host copy of the
+ * state. */
 int mhd_server_submit_ref(mhd_server_t* s, int nx, int ny, int nz, double gamma, int bc, int dtype,
                           const void* host_state, int nsteps, int* req);
 
