@@ -314,3 +314,31 @@ def test_fp64_bitwise_on_scaled_states(B, orc, alpha):
     assert t == tw
     bad = [f for f in range(8) if not np.array_equal(got[f], want[f])]
     assert not bad, (bad, field_errors(got, want))
+
+
+DEGENERATE_CASES = [
+    # (nx, ny, nz): one cell; grids shorter than the stencil's reach (the
+    # boundary map wraps or clamps more than one period); long 1D pencils
+    # along each axis (rows of 1130 wavefronts, marches over 4096 cells)
+    (1, 1, 1),
+    (2, 1, 1),
+    (1, 3, 2),
+    (3, 2, 5),
+    (65536, 1, 1),
+    (1, 4096, 1),
+    (1, 1, 4096),
+]
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("shape", DEGENERATE_CASES)
+def test_fp64_bitwise_on_degenerate_shapes(B, orc, shape, bc):
+    nx, ny, nz = shape
+    s = P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 53)
+    g = orc.Grid(nx, ny, nz, H.GAMMA53, bc)
+    note("bitwise degenerate shape %s bc %d" % (shape, bc))
+    got, (t, _) = gpu_run(B, s, H.GAMMA53, bc, B.MHD_F64, 3)
+    want, tw, _ = orc.run(g, s, 3, 0.7)
+    assert t == tw
+    bad = [f for f in range(8) if not np.array_equal(got[f], want[f])]
+    assert not bad, (bad, field_errors(got, want))
