@@ -48,8 +48,9 @@ enum {
 enum { MHD_BC_PERIODIC = 0, MHD_BC_OUTFLOW = 1 };
 enum { MHD_F32 = 0, MHD_F64 = 1 };
 
-/* Create a solver for an nx x ny x nz grid (each >= 1; sizes need not be
- * powers of two), adiabatic index gamma > 1, boundary condition bc applied on
+/* Create a solver for an nx x ny x nz grid (each >= 1, at most 2^36 cells in
+ * all; sizes need not be powers of two), adiabatic index gamma > 1, boundary
+ * condition bc applied on
  * every axis (periodic wrap, or outflow = zero-gradient copy of cell and face
  * values beyond the edge) and arithmetic type dtype. The handle owns its
  * device memory: two ping-pong copies of the state plus a few scalars. The
@@ -60,7 +61,8 @@ int mhd_create(int nx, int ny, int nz, double gamma, int bc, int dtype, mhd_t** 
 int mhd_destroy(mhd_t* h);
 
 /* Use a caller-owned HIP stream (hipStream_t passed as void*; null = the
- * null stream) for all later work of this handle. */
+ * null stream) for all later work of this handle. Waits for the work already
+ * issued on the previous stream, so the handle's operations stay ordered. */
 int mhd_set_stream(mhd_t* h, void* stream);
 
 /* Replay full steps from HIP graphs (enable = 1, the default) or issue every

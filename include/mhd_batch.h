@@ -52,7 +52,7 @@ int mhd_batch_destroy(mhd_batch_t* b);
 int mhd_batch_set_stream(mhd_batch_t* b, void* stream);
 
 /* Device bytes one problem of this size and dtype holds while it is in a
- * batch (0 for invalid arguments). */
+ * batch (0 for invalid arguments, including grids of more than 2^36 cells). */
 size_t mhd_batch_problem_bytes(int nx, int ny, int nz, int dtype);
 
 /* Add a problem: grid nx x ny x nz (each >= 1), gamma > 1, bc as in mhd.h,

@@ -90,17 +90,32 @@ template <typename F>
 int timed(mhd_solver* h, int kind, F&& f, const char* where)
 {
     hipEvent_t a = nullptr, b = nullptr;
+    // events taken but not queued go back to the pool on every error path
+    auto give_back = [h, &a, &b] {
+        if (a) h->pool.push_back(a);
+        if (b) h->pool.push_back(b);
+        a = b = nullptr;
+    };
     if (h->timing) {
         a = take_event(h);
         b = take_event(h);
-        if (!a || !b) return fail(MHD_ERR_DEVICE, "hipEventCreate failed");
-        HIPCHK(hipEventRecord(a, h->stream), "hipEventRecord");
+        if (!a || !b) {
+            give_back();
+            return fail(MHD_ERR_DEVICE, "hipEventCreate failed");
+        }
+        const hipError_t e = hipEventRecord(a, h->stream);
+        if (e != hipSuccess) {
+            give_back();
+            return hip_fail(e, "hipEventRecord");
+        }
     }
-    HIPCHK(f(), where);
-    if (h->timing) {
-        HIPCHK(hipEventRecord(b, h->stream), "hipEventRecord");
-        h->pending[kind].emplace_back(a, b);
+    hipError_t e = f();
+    if (e == hipSuccess && h->timing) e = hipEventRecord(b, h->stream);
+    if (e != hipSuccess) {
+        give_back();
+        return hip_fail(e, where);
     }
+    if (h->timing) h->pending[kind].emplace_back(a, b);
     return MHD_OK;
 }
 
@@ -289,6 +304,7 @@ static size_t workspace_layout(const Grid& g, size_t es, size_t offs[6])
 size_t mhd_workspace_bytes(int nx, int ny, int nz, int dtype)
 {
     if (nx < 1 || ny < 1 || nz < 1 || (dtype != MHD_F32 && dtype != MHD_F64)) return 0;
+    if ((long long)nx * ny * nz > (1LL << 36)) return 0;   // larger than mhd_create accepts
     mhd::Grid g;
     g.n[0] = nx;
     g.n[1] = ny;
@@ -307,7 +323,9 @@ int mhd_create(int nx, int ny, int nz, double gamma, int bc, int dtype, mhd_t** 
     if (!out) return fail(MHD_ERR_ARG, "null output pointer");
     *out = nullptr;
     if (nx < 1 || ny < 1 || nz < 1) return fail(MHD_ERR_ARG, "grid sizes must be >= 1");
-    if ((long long)nx * ny * nz > (1LL << 40)) return fail(MHD_ERR_ARG, "grid too large");
+    // wavefront and workgroup indices of the sweeps are 32-bit: with at most
+    // 2^36 cells (far beyond device memory) every launch stays below 2^32
+    if ((long long)nx * ny * nz > (1LL << 36)) return fail(MHD_ERR_ARG, "grid too large (more than 2^36 cells)");
     if (!(gamma > 1.0) || !std::isfinite(gamma)) return fail(MHD_ERR_ARG, "gamma must be a finite number > 1");
     if (bc != MHD_BC_PERIODIC && bc != MHD_BC_OUTFLOW) return fail(MHD_ERR_ARG, "unknown boundary condition");
     if (dtype != MHD_F32 && dtype != MHD_F64) return fail(MHD_ERR_ARG, "unknown dtype");
@@ -450,6 +468,9 @@ int mhd_set_graphs(mhd_t* h, int enable)
 int mhd_set_stream(mhd_t* h, void* stream)
 {
     if (int rc = check(h)) return rc;
+    if (int rc = set_current(h)) return rc;
+    // work already issued on the old stream finishes before any on the new one
+    HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
     h->stream = static_cast<hipStream_t>(stream);
     return MHD_OK;
 }

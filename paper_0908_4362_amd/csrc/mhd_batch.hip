@@ -180,9 +180,11 @@ size_t problem_layout(const Grid& g, int dtype, size_t offs[6])
     return off;
 }
 
+// Grid and problem constants a problem may have (at most 2^36 cells: the
+// sweeps index wavefronts and workgroups with 32 bits).
 bool grid_ok(int nx, int ny, int nz, double gamma, int bc)
 {
-    return nx >= 1 && ny >= 1 && nz >= 1 && (long long)nx * ny * nz <= (1LL << 40) && gamma > 1.0 &&
+    return nx >= 1 && ny >= 1 && nz >= 1 && (long long)nx * ny * nz <= (1LL << 36) && gamma > 1.0 &&
            std::isfinite(gamma) && (bc == MHD_BC_PERIODIC || bc == MHD_BC_OUTFLOW);
 }
 

@@ -65,6 +65,7 @@ def test_argument_errors_are_reported_before_device_use(libmhd):
         (4, 4, 4, float("nan"), 0, B.MHD_F64),
         (4, 4, 4, 1.4, 7, B.MHD_F64),
         (4, 4, 4, 1.4, 0, 5),
+        (8192, 8192, 1025, 1.4, 0, B.MHD_F32),   # more than 2^36 cells
     ]
     for args in bad:
         with pytest.raises(B.MHDError) as ei:
@@ -77,6 +78,7 @@ def test_argument_errors_are_reported_before_device_use(libmhd):
     assert B.lib().mhd_destroy(None) == B.MHD_OK
     assert B.mhd_state_bytes(0, 1, 1, B.MHD_F32) == 0
     assert B.mhd_state_bytes(4, 4, 4, B.MHD_F32) >= 2 * 8 * 64 * 4
+    assert B.mhd_state_bytes(8192, 8192, 1025, B.MHD_F32) == 0
     assert h.value is None
 
 
@@ -95,6 +97,7 @@ def test_batch_argument_errors_are_reported_before_device_use(libmhd):
     assert L.mhd_batch_autotune(None, 1) == B.MHD_ERR_ARG
     assert B.mhd_batch_problem_bytes(0, 4, 4, B.MHD_F64) == 0
     assert B.mhd_batch_problem_bytes(4, 4, 4, 3) == 0
+    assert B.mhd_batch_problem_bytes(8192, 8192, 1025, B.MHD_F32) == 0   # more than 2^36 cells
     # two state copies of 8 fields, control block and reduction slots
     for (nx, ny, nz) in ((32, 32, 32), (48, 20, 7), (128, 1, 1)):
         for dt, es in ((B.MHD_F32, 4), (B.MHD_F64, 8)):
