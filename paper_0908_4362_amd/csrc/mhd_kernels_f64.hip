@@ -14,6 +14,9 @@ __global__ void __launch_bounds__(FB) finish_kernel(const unsigned long long* __
                                                     int what, double cfl, Ctl* ctl)
 {
     unsigned long long best = 0ull;
+    // unrolled so that each thread has several loads in flight (up to 80
+    // slots per thread when an x sweep produced them)
+#pragma unroll 8
     for (int k = threadIdx.x; k < nparts; k += FB) best = parts[k] > best ? parts[k] : best;
     best = block_max_u64<FB>(best, threadIdx.x);
     if (threadIdx.x == 0) {
@@ -37,6 +40,7 @@ __global__ void __launch_bounds__(FBB) finish_batch_kernel(const BJob* __restric
     const unsigned long long* parts = jobs[j].parts;
     const unsigned n = td[j + 1].first - td[j].first;
     unsigned long long best = 0ull;
+#pragma unroll 8
     for (unsigned k = threadIdx.x; k < n; k += FBB) best = parts[k] > best ? parts[k] : best;
     best = block_max_u64<FBB>(best, threadIdx.x);
     if (threadIdx.x == 0) {
