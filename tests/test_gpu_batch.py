@@ -250,3 +250,30 @@ def test_batch_argument_errors(B):
         with pytest.raises(B.MHDError):
             B.mhd_batch_autotune(bt.b, 0)
         bt.step(2)   # an empty batch steps nothing
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_batch_of_random_shapes_equals_plain_bitwise(B, dtype):
+    """Thirty problems of seeded random shapes (1 to 90 cells per axis, so
+    single cells, lines, planes and boxes with ragged tiles), boundary
+    conditions and gamma in one batch, stepped in two bursts with problems
+    joining in between: every one bitwise equal to its plain solve."""
+    rng = np.random.Generator(np.random.PCG64(P.MASTER_SEED + 350 + dtype))
+    probs = []
+    for k in range(30):
+        shape = [int(x) for x in rng.integers(1, 91, size=3)]
+        shape[int(rng.integers(0, 3))] = int(rng.integers(1, 6))    # one short axis keeps the batch small
+        nx, ny, nz = shape
+        probs.append((P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 360 + k), float(rng.choice([1.4, H.GAMMA53, 2.0])),
+                      int(rng.integers(0, 2))))
+    note("batch of %d random shapes, dtype %d" % (len(probs), dtype))
+    with B.Batch(dtype) as bt:
+        first = [bt.add(s, gm, bc) for (s, gm, bc) in probs[:20]]
+        bt.step(2)
+        later = [bt.add(s, gm, bc) for (s, gm, bc) in probs[20:]]
+        bt.step(3)
+        for pid, (s, gm, bc), n in [(p, q, 5) for p, q in zip(first, probs[:20])] + \
+                                   [(p, q, 3) for p, q in zip(later, probs[20:])]:
+            want, tw = plain(B, s, gm, bc, dtype, n)
+            assert np.array_equal(bt.get_state(pid), want), (pid, s.shape)
+            assert bt.time(pid) == tw
