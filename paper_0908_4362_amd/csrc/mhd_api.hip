@@ -155,6 +155,14 @@ int ct(mhd_solver* h, int axis, double dt)
 // reverse L_d with the field update first; axis order (x,y,z), (z,x,y),
 // (y,z,x) by s mod 3. With reduce_cmax the last fluid sweep also stores the
 // per-workgroup maxima of the CFL speed of the state it writes.
+//
+// A fluid sweep along an axis of one cell is the identity, bit for bit: every
+// stencil neighbour is that cell, so fluxes, slopes and flux differences are
+// exact zeros and u - dt * 0 = u. Such sweeps are skipped (in pairs, forward
+// and reverse, so the ping-pong copies still end where they started), except
+// the one that produces the c_max maxima. The field sweep along such an axis
+// is not skipped: its constraint update of B_d uses EMFs of neighbouring
+// pencils, which a velocity along d makes non-zero.
 template <typename T>
 int sweeps(mhd_solver* h, long long s, double dt, bool reduce_cmax)
 {
@@ -162,12 +170,14 @@ int sweeps(mhd_solver* h, long long s, double dt, bool reduce_cmax)
     const int* p = perm[((s % 3) + 3) % 3];
     int rc;
     for (int a = 0; a < 3; a++) {
-        if ((rc = fluid<T>(h, p[a], dt))) return rc;
+        if (h->g.n[p[a]] > 1 || (reduce_cmax && a == 0))
+            if ((rc = fluid<T>(h, p[a], dt))) return rc;
         if ((rc = ct<T>(h, p[a], dt))) return rc;
     }
     for (int a = 2; a >= 0; a--) {
         if ((rc = ct<T>(h, p[a], dt))) return rc;
-        if ((rc = fluid<T>(h, p[a], dt, reduce_cmax && a == 0))) return rc;
+        if (h->g.n[p[a]] > 1 || (reduce_cmax && a == 0))
+            if ((rc = fluid<T>(h, p[a], dt, reduce_cmax && a == 0))) return rc;
     }
     return MHD_OK;
 }
