@@ -262,3 +262,32 @@ def test_graph_replay_equals_direct_launches(B):
                 assert a == b
             else:
                 assert np.array_equal(a, b)
+
+
+def test_stream_switch_keeps_the_handle_ordered(B):
+    """An asynchronous device copy-out still queued on the old stream when
+    the handle switches streams: the steps issued on the new stream (which
+    overwrite the copy being read within their first sweeps) must wait for
+    it, so the copy holds the state from before them, bit for bit."""
+    import torch
+
+    n = 128
+    s = P.random_smooth(n, n, n, seed=P.MASTER_SEED + 44)
+    a, b = torch.cuda.Stream(), torch.cuda.Stream()
+    out = torch.empty(s.shape, dtype=torch.float64, device="cuda")
+    note("stream switch with a copy-out in flight")
+    with B.Solver(n, n, n, H.GAMMA53, 0, B.MHD_F64) as sv:
+        B.mhd_set_stream(sv.h, a)
+        sv.set_state(s)
+        sv.step(2)
+        mid = sv.get_state()
+        B.mhd_get_state_device(sv.h, out)     # queued on a
+        B.mhd_set_stream(sv.h, b)
+        sv.step(3)                            # queued on b
+        end = sv.get_state()
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), mid)
+    with B.Solver(n, n, n, H.GAMMA53, 0, B.MHD_F64) as ref:
+        ref.set_state(s)
+        ref.step(5)
+        assert np.array_equal(end, ref.get_state())
