@@ -143,7 +143,11 @@ int ct(mhd_solver* h, int axis, double dt)
     const T* bin = static_cast<const T*>(h->b[h->bcur]);
     T* bout = static_cast<T*>(h->b[h->bcur ^ 1]);
     int rc = timed(h, MHD_K_CT_X + axis,
-                   [&] { return mhd::launch_ct<T>(axis, u, bin, bout, h->g, h->ctl, dt, h->stream); },
+                   [&] {
+                       return axis > 0 && h->g.n[axis] == 1
+                                  ? mhd::launch_ct_flat<T>(axis, u, bin, bout, h->g, h->ctl, dt, h->stream)
+                                  : mhd::launch_ct<T>(axis, u, bin, bout, h->g, h->ctl, dt, h->stream);
+                   },
                    "field sweep launch");
     if (rc) return rc;
     h->bcur ^= 1;
@@ -162,7 +166,8 @@ int ct(mhd_solver* h, int axis, double dt)
 // and reverse, so the ping-pong copies still end where they started), except
 // the one that produces the c_max maxima. The field sweep along such an axis
 // is not skipped: its constraint update of B_d uses EMFs of neighbouring
-// pencils, which a velocity along d makes non-zero.
+// pencils, which a velocity along d makes non-zero; along y or z it runs in
+// closed form (launch_ct_flat).
 template <typename T>
 int sweeps(mhd_solver* h, long long s, double dt, bool reduce_cmax)
 {

@@ -57,6 +57,12 @@ hipError_t launch_fluid(int axis, const T* u_in, T* u_out, const T* b, Grid g, d
 template <typename T>
 hipError_t launch_ct(int axis, const T* u, const T* b_in, T* b_out, Grid g, const Ctl* ctl, double dt,
                      hipStream_t s);
+// The field sweep along axis 1 or 2 when that axis has one cell: the fixed
+// point of the marching pipeline, evaluated per cell (same results bit for
+// bit, one pass over the fields instead of a warm-up per chunk).
+template <typename T>
+hipError_t launch_ct_flat(int axis, const T* u, const T* b_in, T* b_out, Grid g, const Ctl* ctl, double dt,
+                          hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Batched launches: one launch runs one sub-operation for many independent

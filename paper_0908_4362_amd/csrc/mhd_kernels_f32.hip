@@ -1,6 +1,7 @@
 // Single-precision instantiation of the step kernels (FMA contraction allowed).
 #include "mhd_batch_impl.h"
 #include "mhd_diag_impl.h"
+#include "mhd_flat_impl.h"
 
 namespace mhd {
 template hipError_t launch_cfl<float>(const float*, const float*, Grid, double, unsigned long long*, int*,
@@ -10,6 +11,8 @@ template hipError_t launch_fluid<float>(int, const float*, float*, const float*,
                                         unsigned long long*, int*, hipStream_t);
 template hipError_t launch_ct<float>(int, const float*, const float*, float*, Grid, const Ctl*, double,
                                      hipStream_t);
+template hipError_t launch_ct_flat<float>(int, const float*, const float*, float*, Grid, const Ctl*, double,
+                                           hipStream_t);
 template void tile_default<float>(const Grid&, int, int*, int*);
 template void tile_candidates<float>(const Grid&, int, std::vector<std::pair<int, int>>&);
 template unsigned tile_blocks<float>(const Grid&, int, int, int);

@@ -3,6 +3,7 @@
 // expression rounds exactly as the CPU oracle's.
 #include "mhd_batch_impl.h"
 #include "mhd_diag_impl.h"
+#include "mhd_flat_impl.h"
 
 namespace mhd {
 namespace {
@@ -81,6 +82,8 @@ template hipError_t launch_fluid<double>(int, const double*, double*, const doub
                                          double, unsigned long long*, int*, hipStream_t);
 template hipError_t launch_ct<double>(int, const double*, const double*, double*, Grid, const Ctl*, double,
                                       hipStream_t);
+template hipError_t launch_ct_flat<double>(int, const double*, const double*, double*, Grid, const Ctl*, double,
+                                           hipStream_t);
 template void tile_default<double>(const Grid&, int, int*, int*);
 template void tile_candidates<double>(const Grid&, int, std::vector<std::pair<int, int>>&);
 template unsigned tile_blocks<double>(const Grid&, int, int, int);

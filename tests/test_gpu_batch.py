@@ -277,3 +277,22 @@ def test_batch_of_random_shapes_equals_plain_bitwise(B, dtype):
             want, tw = plain(B, s, gm, bc, dtype, n)
             assert np.array_equal(bt.get_state(pid), want), (pid, s.shape)
             assert bt.time(pid) == tw
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_flat_axes_match_the_marching_field_sweep(B, dtype):
+    """Plain solves update the field along an axis of one cell in closed form
+    (one thread per cell); batched solves keep the marching pipeline there.
+    Planes and lines in every orientation, both boundary conditions, six full
+    steps (each sweep order twice): the two bitwise equal."""
+    shapes = [(37, 29, 1), (41, 1, 23), (1, 19, 27), (53, 1, 1), (1, 31, 1), (1, 1, 29), (70, 1, 3)]
+    probs = [(P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 380 + k), H.GAMMA53, k % 2)
+             for k, (nx, ny, nz) in enumerate(shapes)]
+    note("flat-axis shapes, dtype %d" % dtype)
+    with B.Batch(dtype) as bt:
+        ids = [bt.add(s, gm, bc) for (s, gm, bc) in probs]
+        bt.step(6)
+        for pid, (s, gm, bc) in zip(ids, probs):
+            want, tw = plain(B, s, gm, bc, dtype, 6)
+            assert np.array_equal(bt.get_state(pid), want), s.shape
+            assert bt.time(pid) == tw
