@@ -162,12 +162,18 @@ int ct(mhd_solver* h, int axis, double dt)
 //
 // A fluid sweep along an axis of one cell is the identity, bit for bit: every
 // stencil neighbour is that cell, so fluxes, slopes and flux differences are
-// exact zeros and u - dt * 0 = u. Such sweeps are skipped (in pairs, forward
-// and reverse, so the ping-pong copies still end where they started), except
-// the one that produces the c_max maxima. The field sweep along such an axis
-// is not skipped: its constraint update of B_d uses EMFs of neighbouring
-// pencils, which a velocity along d makes non-zero; along y or z it runs in
-// closed form (launch_ct_flat).
+// exact zeros and u - dt * 0 = u. Such sweeps are skipped, always in pairs
+// (forward and reverse), so the ping-pong copies still end where they started.
+// When the skipped pair was the one whose reverse sweep produces the c_max
+// maxima, a standalone pass over the final state produces them instead (the
+// same per-cell speeds, so the same maximum bit for bit; it reads the state
+// once and writes nothing, where the two sweeps read it twice and wrote it
+// twice). The field sweep along such an axis is not skipped: its constraint
+// update of B_d uses EMFs of neighbouring pencils, which a velocity along d
+// makes non-zero; along y or z it runs in closed form (launch_ct_flat).
+template <typename T>
+int cfl_parts(mhd_solver* h);
+
 template <typename T>
 int sweeps(mhd_solver* h, long long s, double dt, bool reduce_cmax)
 {
@@ -175,15 +181,16 @@ int sweeps(mhd_solver* h, long long s, double dt, bool reduce_cmax)
     const int* p = perm[((s % 3) + 3) % 3];
     int rc;
     for (int a = 0; a < 3; a++) {
-        if (h->g.n[p[a]] > 1 || (reduce_cmax && a == 0))
+        if (h->g.n[p[a]] > 1)
             if ((rc = fluid<T>(h, p[a], dt))) return rc;
         if ((rc = ct<T>(h, p[a], dt))) return rc;
     }
     for (int a = 2; a >= 0; a--) {
         if ((rc = ct<T>(h, p[a], dt))) return rc;
-        if (h->g.n[p[a]] > 1 || (reduce_cmax && a == 0))
+        if (h->g.n[p[a]] > 1)
             if ((rc = fluid<T>(h, p[a], dt, reduce_cmax && a == 0))) return rc;
     }
+    if (reduce_cmax && h->g.n[p[0]] == 1) return cfl_parts<T>(h);
     return MHD_OK;
 }
 

@@ -183,19 +183,28 @@ def test_step_dt_matches_oracle(B, orc):
         assert H.rel_linf(got[f], want[f]) <= 1e-11, f
 
 
-def test_timing_counts_launches(B):
-    with B.Solver(40, 30, 20, H.GAMMA53) as sv:
-        sv.set_state(P.random_smooth(40, 30, 20, seed=P.MASTER_SEED + 45))
+@pytest.mark.parametrize("shape,want", [
+    # per step: the dt rule (the first step also runs a standalone c_max
+    # pass; later steps take the maxima the last fluid sweep stored) and two
+    # launches of each directional sub-operation
+    ((40, 30, 20), [4, 6, 6, 6, 6, 6, 6]),
+    # fluid sweeps along an axis of one cell are skipped; where the skipped
+    # pair would have produced the c_max maxima (sweep orders starting with
+    # that axis: z at s = 1, y at s = 2) a standalone pass produces them
+    ((40, 30, 1), [5, 6, 6, 0, 6, 6, 6]),
+    ((40, 1, 1), [6, 6, 0, 0, 6, 6, 6]),
+])
+def test_timing_counts_launches(B, shape, want):
+    nx, ny, nz = shape
+    with B.Solver(nx, ny, nz, H.GAMMA53) as sv:
+        sv.set_state(P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 45))
         B.mhd_timing(sv.h, True)
         sv.step(3)
         counts = [B.mhd_timing_read(sv.h, k)[1] for k in range(B.MHD_K_COUNT)]
         ms = [B.mhd_timing_read(sv.h, k)[0] for k in range(B.MHD_K_COUNT)]
         B.mhd_timing(sv.h, False)
-    # per step: the dt rule (the first step also runs a standalone c_max
-    # pass; later steps take the maxima the last fluid sweep stored) and two
-    # launches of each directional sub-operation
-    assert counts == [4, 6, 6, 6, 6, 6, 6]
-    assert all(m > 0 for m in ms)
+    assert counts == want
+    assert all((m > 0) == (c > 0) for m, c in zip(ms, counts))
 
 
 def test_bound_workspace_equals_owned_memory(B):
