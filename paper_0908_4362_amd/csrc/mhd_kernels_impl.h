@@ -424,12 +424,15 @@ struct MarchTile {
 // z. The FP64 field sweep keeps them along z (xwide false): it reads the -z
 // and +z neighbours of rho and m_d, which a workgroup along z shares (2 %
 // faster that way). A z sweep's transverse neighbours are adjacent rows, so
-// its wavefronts stay along y.
-__host__ __device__ inline int march_wx(int axis, int nx, bool xwide)
+// its wavefronts stay along y. Either way a transverse axis shorter than the
+// workgroup (nt = 1 on a plane) would leave wavefronts without a pencil, so
+// the workgroup then puts along x as many as the transverse axis cannot take.
+__host__ __device__ inline int march_wx(int axis, int nx, int nt, bool xwide)
 {
     int wx = 1;
     if (axis == 1 && xwide)
         while (wx < MW && 128 * wx <= nx) wx *= 2;
+    while (wx < MW && nt * wx < MW) wx *= 2;
     return wx;
 }
 
@@ -442,7 +445,7 @@ __device__ __forceinline__ MarchTile march_tile(const Grid& g, int chunk, unsign
 {
     constexpr int TA = (D == 1) ? 2 : 1;
     const int nx = g.n[0], nd = g.n[D], nt = g.n[TA];
-    const unsigned wx = (unsigned)march_wx(D, nx, XWIDE), wt = MW / wx;
+    const unsigned wx = (unsigned)march_wx(D, nx, nt, XWIDE), wt = MW / wx;
     const unsigned ntx = (nx + 64 * wx - 1) / (64 * wx), ntg = (nt + wt - 1) / wt;
     const unsigned xt = lb % ntx, rest = lb / ntx;
     const unsigned tg = rest % ntg, ch = rest / ntg;
@@ -1034,7 +1037,7 @@ int march_chunk(const Grid& g, int d, int ghost, long long target)
 static unsigned march_blocks(const Grid& g, int axis, int chunk, bool xwide)
 {
     const int ta = (axis == 1) ? 2 : 1;
-    const int wx = march_wx(axis, g.n[0], xwide), wt = MW / wx;
+    const int wx = march_wx(axis, g.n[0], g.n[ta], xwide), wt = MW / wx;
     return (unsigned)(((g.n[0] + 64 * wx - 1) / (64 * wx)) * ((g.n[ta] + wt - 1) / wt) *
                       ((g.n[axis] + chunk - 1) / chunk));
 }
