@@ -92,7 +92,17 @@ def run_gpu(B, P, n, dtype, warmup, steps, stream):
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "blast256_traffic.txt")
-KERNEL_SOURCE = os.path.join(HERE, "paper_0908_4362_amd", "csrc", "mhd_kernels_impl.h")
+# the kernels' source and the compiler flags they are built with
+KERNEL_SOURCES = (os.path.join(HERE, "paper_0908_4362_amd", "csrc", "mhd_kernels_impl.h"),
+                  os.path.join(HERE, "paper_0908_4362_amd", "build.py"))
+
+
+def kernel_fingerprint():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(prec, kind, n):
@@ -100,8 +110,7 @@ def measured_traffic(prec, kind, n):
     summary is for another workload or the kernel source has changed since the counters were taken."""
     if n != 256 or not os.path.exists(TRAFFIC_FILE):
         return None
-    with open(KERNEL_SOURCE, "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+    sha = kernel_fingerprint()
     table, src = {}, None
     with open(TRAFFIC_FILE) as fh:
         for line in fh:

@@ -1,4 +1,7 @@
-// Single-precision instantiation of the step kernels (FMA contraction allowed).
+// Single-precision instantiation of the step kernels. Built with
+// -ffp-contract=on: a multiply and an add fuse into an FMA only within one
+// source expression, never across statements, so results do not depend on
+// where a loop's unrolled copies place an iteration (chunk layout, tiles).
 #include "mhd_batch_impl.h"
 #include "mhd_diag_impl.h"
 #include "mhd_flat_impl.h"

@@ -71,7 +71,7 @@ size_t reduce_capacity(const Grid& g)
     size_t cap = (size_t)reduce_blocks(g);
     cap = std::max(cap, (size_t)x_wave_blocks(g));
     for (int axis = 1; axis <= 2; axis++)
-        cap = std::max(cap, (size_t)march_blocks(g, axis, march_chunk(g, axis, GF, kFluidMarchWaves), true));
+        cap = std::max(cap, (size_t)march_blocks(g, axis, march_chunk(g, axis, GF, kFluidMarchWaves, true), true));
     return cap;
 }
 

@@ -31,7 +31,8 @@ namespace {
 // so the double-precision path reproduces it bit for bit (the upwind choice of
 // the field update is discontinuous at exact ties, which symmetric problems
 // produce, so only identical arithmetic makes both take the same branch).
-// FP32 instantiations use FMA and one reciprocal of rho per cell.
+// FP32 instantiations use FMA within an expression and one reciprocal of rho
+// per cell.
 template <typename T>
 constexpr bool kExact = std::is_same<T, double>::value;
 
@@ -1017,8 +1018,12 @@ int reduce_blocks(const Grid& g)
 // ghost depths, where the warm-up (two ghost depths per chunk) would cost
 // half the work. Mid-size and 2D grids need the short chunks to fill the
 // device (128^3 blast step 24-31 % faster, Orszag-Tang 512^2 37 %, than
-// with a floor of sixteen ghost depths); 256^3 takes 128-cell chunks.
-int march_chunk(const Grid& g, int d, int ghost, long long target)
+// with a floor of sixteen ghost depths); 256^3 takes 128-cell chunks. With
+// `fill` (a launch that has the device to itself) a grid that would still
+// give fewer than target / 2 wavefronts goes down to two ghost depths: the
+// doubled warm-up costs less than the idle device (Orszag-Tang 512^2 17 %
+// faster); a batch fills the device with other problems and keeps four.
+int march_chunk(const Grid& g, int d, int ghost, long long target, bool fill = false)
 {
     const int ta = (d == 1) ? 2 : 1;
     const long long waves = ((g.n[0] + 63) / 64) * (long long)g.n[ta];
@@ -1026,7 +1031,8 @@ int march_chunk(const Grid& g, int d, int ghost, long long target)
     long long want = target / (waves > 0 ? waves : 1);
     if (want < 1) want = 1;
     int chunk = (int)((nd + want - 1) / want);
-    const int minchunk = 4 * ghost;
+    int minchunk = 4 * ghost;
+    if (fill && waves * ((nd + minchunk - 1) / minchunk) < target / 2) minchunk = 2 * ghost;
     if (chunk < minchunk) chunk = minchunk;
     if (chunk > nd) chunk = nd;
     return chunk;
@@ -1071,7 +1077,7 @@ static void fluid_launch(int axis, const T* u_in, T* u_out, const T* b, Grid g, 
         hipLaunchKernelGGL((fluid_x_wave<T, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
                            parts);
     } else {
-        const int chunk = march_chunk(g, axis, GF, kFluidMarchWaves);
+        const int chunk = march_chunk(g, axis, GF, kFluidMarchWaves, true);
         nb = march_blocks(g, axis, chunk, kMarchXWide<T, false>);
         const dim3 block(64, MW);
         if (axis == 1)
@@ -1102,7 +1108,7 @@ hipError_t launch_ct(int axis, const T* u, const T* b_in, T* b_out, Grid g, cons
     if (axis == 0) {
         hipLaunchKernelGGL((ct_x_wave<T>), dim3(ct_x_wave_blocks(g)), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt);
     } else {
-        const int chunk = march_chunk(g, axis, GB, kCtMarchWaves<T>);
+        const int chunk = march_chunk(g, axis, GB, kCtMarchWaves<T>, true);
         const dim3 grid(march_blocks(g, axis, chunk, kMarchXWide<T, true>)), block(64, MW);
         if (axis == 1)
             hipLaunchKernelGGL((ct_march<T, 1>), grid, block, 0, s, u, b_in, b_out, g, ctl, dt, chunk);

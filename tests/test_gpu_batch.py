@@ -161,10 +161,14 @@ def test_batch_graph_replay_equals_eager(B):
         assert np.array_equal(g, e)
 
 
-def test_batch_autotune_keeps_results(B):
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_batch_autotune_keeps_results(B, dtype):
+    """Autotuned chunk lengths differ from the plain solve's; results may not
+    (in FP32 too: FMA contraction stays within one expression, so the unrolled
+    marching loop rounds every cell the same wherever its chunk starts)."""
     probs = mixed_problems()
-    note("autotune")
-    with B.Batch(B.MHD_F64) as bt:
+    note("autotune, dtype %d" % dtype)
+    with B.Batch(dtype) as bt:
         ids = [bt.add(s, gm, bc) for (s, gm, bc) in probs]
         bt.step(2)
         bt.autotune(2)
@@ -179,7 +183,7 @@ def test_batch_autotune_keeps_results(B):
                     assert p0 <= s.shape[3 - axis]
         bt.step(3)
         for pid, (s, gm, bc) in zip(ids, probs):
-            assert np.array_equal(bt.get_state(pid), plain(B, s, gm, bc, 1, 5)[0]), pid
+            assert np.array_equal(bt.get_state(pid), plain(B, s, gm, bc, dtype, 5)[0]), pid
 
 
 def test_batch_failure_is_isolated(B):
