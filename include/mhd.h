@@ -19,6 +19,16 @@
  *   (eq. equat_b). Cells have unit width, so times are in cell-crossing units:
  *   a physical time t on a box of n cells per unit length is t * n.
  *
+ * Arithmetic: MHD_F64 evaluates every expression of the scheme in IEEE double
+ * precision in a fixed order, without fused multiply-adds, with correctly
+ * rounded quotients (for operands in the normal range) and square roots, so
+ * it equals a plain serial evaluation bit for bit. MHD_F32 fuses a multiply and
+ * an add within one expression and uses the hardware reciprocal and square root
+ * (1 ulp). In both, a step is deterministic and its result does not depend on
+ * how the work is laid out on the device (grid shape of the launches, march
+ * chunks, batch tiles): a batched or served problem gets the same bits as a
+ * plain handle.
+ *
  * Return codes: MHD_OK (0) or a negative MHD_ERR_* value; after an error,
  * mhd_last_error() returns a message (thread-local). No exception crosses the
  * ABI. A handle is not thread-safe; distinct handles are independent. All
