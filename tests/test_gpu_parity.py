@@ -327,6 +327,11 @@ DEGENERATE_CASES = [
     (65536, 1, 1),
     (1, 4096, 1),
     (1, 1, 4096),
+    # planes with one cell along y or x: closed-form field sweep along y,
+    # x sweeps over rows of one cell, marches whose transverse axis has one
+    # cell (workgroups then side by side along x)
+    (70, 1, 33),
+    (1, 45, 37),
 ]
 
 
