@@ -391,12 +391,16 @@ PAPER_CONFIGS = [
 ]
 
 
-def run_paper_configs(B, P, steps=20, warmup=3):
+def run_paper_configs(B, P, steps=20, warmup=3, only=None):
+    """The paper's timing workloads (all, or the one at index `only`, which also reports per-kernel
+    ms/step from an instrumented pass of as many steps)."""
     import torch
 
     out = []
     stream = torch.cuda.Stream()   # a stream of its own: steps replay from graphs
-    for name, kind, n, paper_ms in PAPER_CONFIGS:
+    for idx, (name, kind, n, paper_ms) in enumerate(PAPER_CONFIGS):
+        if only is not None and idx != only:
+            continue
         if kind == "brio_wu":
             s, gamma, bc = P.brio_wu(n), 2.0, B.MHD_BC_OUTFLOW
         elif kind == "orszag_tang":
@@ -416,8 +420,17 @@ def run_paper_configs(B, P, steps=20, warmup=3):
                 sv.step(steps, 0.7)
                 torch.cuda.synchronize()
                 ms = (time.perf_counter() - t0) * 1e3 / steps
+                kern = None
+                if only is not None:
+                    B.mhd_timing(sv.h, True)
+                    sv.step(steps, 0.7)
+                    torch.cuda.synchronize()
+                    kern = {k: round(B.mhd_timing_read(sv.h, i)[0] / steps, 4) for i, k in enumerate(B.KERNEL_KINDS)}
+                    B.mhd_timing(sv.h, False)
             row[label] = {"ms_per_step": round(ms, 4), "cell_updates_per_s": round(nx * ny * nz / ms * 1e3, 1),
                           "paper_gtx480_ms_per_step": pms, "speedup_vs_paper": round(pms / ms, 1)}
+            if kern is not None:
+                row[label]["kernels_ms_per_step"] = kern
         out.append(row)
     return out
 
@@ -467,6 +480,9 @@ def main():
     ap.add_argument("--batch-tune", type=int, default=3, help="autotuner launches per candidate (0: off)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--no-paper-configs", action="store_true", help="skip the paper's own timing workloads")
+    ap.add_argument("--paper-only", type=int, default=None, choices=range(len(PAPER_CONFIGS)),
+                    help="run only this one of the paper's timing workloads (0 Brio-Wu 4096, 1 Orszag-Tang 512^2, "
+                         "2 Orszag-Tang 1024^2, 3 blast 128^3), with per-kernel times, and print its JSON line")
     ap.add_argument("--serve-count", type=int, default=96)
     ap.add_argument("--serve-rates", default="0.5,1.0", help="arrival rates as fractions of saturation")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
@@ -489,6 +505,10 @@ def main():
     from paper_0908_4362_amd import problems as P
 
     torch.cuda.set_device(0)
+    if args.paper_only is not None:
+        print("bench: paper timing workload %d only" % args.paper_only, file=sys.stderr, flush=True)
+        print(json.dumps(run_paper_configs(B, P, args.steps, args.warmup, only=args.paper_only)[0]), flush=True)
+        return
     stream = torch.cuda.Stream()   # a stream of its own (default priority): full steps replay from graphs
     n = args.n
     ncell = n ** 3
