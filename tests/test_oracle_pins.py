@@ -340,6 +340,94 @@ def test_field_sweep_ignores_grid_scale_velocity(orc, d):
         np.testing.assert_allclose(o1[5 + c], o0[5 + c], rtol=0, atol=1e-14)
 
 
+def _axis_state(orc, d, e, nd, ne, rho, md, bvec, b_e=None):
+    """State with n_d = nd cells along the sweep axis d, ne along e and one
+    along the third axis; rho and the d-momentum are given per e-row (arrays
+    of length ne, uniform along d), B is uniform bvec except that the face
+    values of B_e along d may be given (array of length nd)."""
+    dims = [1, 1, 1]
+    dims[d] = nd
+    dims[e] = ne
+    nx, ny, nz = dims
+    s = P.uniform(nx, ny, nz, rho=1.0, vel=(0.0, 0.0, 0.0), p=1.0, bvec=bvec)
+    shape_e = [1, 1, 1]
+    shape_e[2 - e] = ne
+    s[0] = np.broadcast_to(np.asarray(rho, dtype=float).reshape(shape_e), s[0].shape)
+    s[1 + d] = np.broadcast_to(np.asarray(md, dtype=float).reshape(shape_e), s[0].shape)
+    if b_e is not None:
+        shape_d = [1, 1, 1]
+        shape_d[2 - d] = nd
+        s[5 + e] = np.broadcast_to(np.asarray(b_e, dtype=float).reshape(shape_d), s[0].shape)
+    return s, orc.Grid(nx, ny, nz, H.GAMMA53)
+
+
+def _along(a, d):
+    """The values of a field along axis d (all other axes have one cell)."""
+    return np.asarray(a).reshape(-1) if a.size == a.shape[2 - d] else None
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_field_sweep_upwind_tie_takes_the_next_cell(orc, d):
+    # eq. first_flux: the upwind EMF at edge i+1/2 takes cell i when the edge
+    # velocity is > 0 and cell i+1 when it is <= 0. Face velocity +2 on four
+    # cells and -2 on the next four (periodic, 8 cells): after the 1-2-1
+    # smoothing v = (1, 2, 2, 1, -1, -2, -2, -1), so the edges 3+1/2 and
+    # 7+1/2 have an edge velocity of exactly 0. With B_e = 1 and dt = 1/4 the
+    # two stages, worked by hand in exact rationals:
+    #   first order  g1(i+1/2) = (1, 2, 2, -1, -2, -2, -1, 1)   (ties take q(i+1))
+    #   half step    B^(1/2)   = (1, 7/8, 1, 11/8, 9/8, 1, 7/8, 3/4)
+    #   v B^(1/2)    qh        = (1, 7/4, 2, 11/8, -9/8, -2, -7/4, -3/4)
+    #   slopes       s         = (21/40, 3/16, 0, -1/2, -35/54, 0, 1/5, 7/11)
+    #   EMF          G(i+1/2)  = (61/40, 31/16, 2, -103/216, -2, -39/20, -61/44, 19/40)
+    # and B_e - dt (G(i+1/2) - G(i-1/2)) below. Taking cell i at the two ties
+    # instead gives other values in cells 0, 2, 3, 4, 5 and 7.
+    from fractions import Fraction as Fr
+
+    e = (d + 1) % 3
+    s, g = _axis_state(orc, d, e, 8, 1, [1.0], [0.0], (0.3, 0.3, 0.3), b_e=np.ones(8))
+    shape_d = [1, 1, 1]
+    shape_d[2 - d] = 8
+    s[1 + d] = np.array([2.0] * 4 + [-2.0] * 4).reshape(shape_d)
+    out = orc.ct_sweep(g, s, d, 0.25)
+    G = [Fr(61, 40), Fr(31, 16), Fr(2), Fr(-103, 216), Fr(-2), Fr(-39, 20), Fr(-61, 44), Fr(19, 40)]
+    want = [1 - Fr(1, 4) * (G[i] - G[i - 1]) for i in range(8)]
+    assert want[3] == Fr(1399, 864) and want[4] == Fr(1193, 864)
+    got = out[5 + e].reshape(-1)
+    np.testing.assert_allclose(got, [float(w) for w in want], rtol=0, atol=1e-14)
+    # the third component (0.3, same face velocity) is advected alike: every
+    # step is homogeneous of degree one in B, so it ends at 0.3 times B_e;
+    # B_d sees no EMF difference across the one-cell axes
+    f = (d + 2) % 3
+    np.testing.assert_allclose(out[5 + f].reshape(-1), [0.3 * float(w) for w in want], rtol=0, atol=1e-14)
+    assert np.array_equal(out[5 + d], s[5 + d])
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_field_sweep_face_velocity_is_mass_weighted(orc, d):
+    # Alg. 2 step 4: the velocity on an e-face is found from the updated
+    # density and momentum of the two cells sharing it. Rows along e with
+    # (rho, m_d) = (3, 0), (1, 1), (1, 1), uniform along d (periodic): the
+    # face velocity (m1 + m2) / (rho1 + rho2) is 1/4 on the lower e-faces of
+    # rows 0 and 1 and 1 on that of row 2 (the mean of the two cell
+    # velocities would give 1/2, 1/2, 1). With B_e uniform the EMF on a face
+    # is v B_e exactly (smoothing and limiter see constant data), so the
+    # constraint update of B_d in row r is dt B_e (v(r+1) - v(r)):
+    # (0, 3/4, -3/4) dt B_e mass-weighted, (0, 1/2, -1/2) dt B_e for the mean.
+    e = (d + 1) % 3
+    be, bd, dt = 0.5, 0.3, 0.5
+    bvec = [0.0, 0.0, 0.0]
+    bvec[d] = bd
+    bvec[e] = be
+    s, g = _axis_state(orc, d, e, 4, 3, [3.0, 1.0, 1.0], [0.0, 1.0, 1.0], tuple(bvec))
+    out = orc.ct_sweep(g, s, d, dt)
+    shape_e = [1, 1, 1]
+    shape_e[2 - e] = 3
+    want = bd + dt * be * np.array([0.0, 0.75, -0.75]).reshape(shape_e)
+    np.testing.assert_allclose(out[5 + d], np.broadcast_to(want, out[5 + d].shape), rtol=0, atol=1e-15)
+    # the advected component is uniform along d and stays unchanged
+    np.testing.assert_allclose(out[5 + e], s[5 + e], rtol=0, atol=1e-15)
+
+
 @pytest.mark.slow
 def test_sod_converges_to_exact_riemann_solution(orc):
     # B = 0 reduces the scheme to a relaxing-TVD Euler solver: its density
