@@ -32,8 +32,7 @@ struct mhd_solver {
     int ucur, bcur;       // current copies
     Ctl* ctl;             // device control block
     unsigned long long* parts;  // per-workgroup maxima: [0, cap) c_max, [cap, 2 cap) div B
-    size_t cap;
-    int nparts;           // parts the last c_max producer wrote
+    size_t cap;           // (the count of c_max slots written last lives in ctl->nparts)
     hipStream_t stream;
     long long s;          // step counter (host mirror; the sweep order needs it on the host)
     int device;
@@ -128,7 +127,7 @@ int fluid(mhd_solver* h, int axis, double dt, bool with_cfl = false)
     int rc = timed(h, MHD_K_FLUID_X + axis,
                    [&] {
                        return mhd::launch_fluid<T>(axis, uin, uout, b, h->g, h->gamma, h->ctl, dt,
-                                                   with_cfl ? h->parts : nullptr, &h->nparts, h->stream);
+                                                   with_cfl ? h->parts : nullptr, h->stream);
                    },
                    "fluid sweep launch");
     if (rc) return rc;
@@ -201,7 +200,7 @@ int cfl_parts(mhd_solver* h)
     const T* u = static_cast<const T*>(h->u[h->ucur]);
     const T* b = static_cast<const T*>(h->b[h->bcur]);
     return timed(h, MHD_K_CFL,
-                 [&] { return mhd::launch_cfl<T>(u, b, h->g, h->gamma, h->parts, &h->nparts, h->stream); },
+                 [&] { return mhd::launch_cfl<T>(u, b, h->g, h->gamma, h->parts, h->ctl, h->stream); },
                  "cfl launch");
 }
 
@@ -215,7 +214,9 @@ void drop_graphs(mhd_solver* h)
 
 // One full step (the dt rule on the previous step's c_max slots, then the 12
 // sweeps) captured in a graph for sweep order q and launched; captured again
-// when cfl changes.
+// when cfl changes. The finisher takes the slot count from the control block,
+// where the producing launch stored it, so a replay reduces the right slots
+// whatever produced them (the previous step in any sweep order, mhd_cmax).
 template <typename T>
 int graph_step(mhd_solver* h, int q, double cfl)
 {
@@ -226,7 +227,7 @@ int graph_step(mhd_solver* h, int q, double cfl)
             h->exec[q] = nullptr;
         }
         HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        hipError_t e = mhd::launch_finish(h->parts, h->nparts, 0, cfl, h->ctl, h->stream);
+        hipError_t e = mhd::launch_finish(h->parts, 0, 0, cfl, h->ctl, h->stream);
         int rc = e == hipSuccess ? sweeps<T>(h, h->s, -1.0, true) : hip_fail(e, "dt launch");
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(h->stream, &graph);
@@ -264,7 +265,7 @@ int full_steps(mhd_solver* h, int n, double cfl)
         } else {
             if (!h->cmax_valid && (rc = cfl_parts<T>(h))) return rc;
             rc = timed(h, MHD_K_CFL,
-                       [&] { return mhd::launch_finish(h->parts, h->nparts, 0, cfl, h->ctl, h->stream); },
+                       [&] { return mhd::launch_finish(h->parts, 0, 0, cfl, h->ctl, h->stream); },
                        "dt launch");
             if (rc) return rc;
             rc = sweeps<T>(h, h->s, -1.0, true);
@@ -382,7 +383,6 @@ int mhd_create(int nx, int ny, int nz, double gamma, int bc, int dtype, mhd_t** 
     }
     const size_t N = (size_t)h->g.N;
     h->cap = mhd::reduce_capacity(h->g);
-    h->nparts = 0;
     void* mem[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     const size_t sizes[6] = {5 * N * h->esize, 5 * N * h->esize, 3 * N * h->esize, 3 * N * h->esize, sizeof(Ctl),
                              2 * h->cap * sizeof(unsigned long long)};
@@ -629,7 +629,7 @@ int mhd_cmax(mhd_t* h, double* out)
     if (int rc = set_current(h)) return rc;
     int rc = h->dtype == MHD_F64 ? cfl_parts<double>(h) : cfl_parts<float>(h);
     if (rc) return rc;
-    HIPCHK(mhd::launch_finish(h->parts, h->nparts, 0, 0.0, h->ctl, h->stream), "cmax finish launch");
+    HIPCHK(mhd::launch_finish(h->parts, 0, 0, 0.0, h->ctl, h->stream), "cmax finish launch");
     h->cmax_valid = true;
     Ctl c;
     if (int rc2 = read_ctl(h, &c)) return rc2;

@@ -89,7 +89,7 @@ __global__ void init_ctl_kernel(Ctl* c)
         c->cmax = 0.0;
         c->divb = 0.0;
         c->status = 0;
-        c->pad = 0;
+        c->nparts = 0;
     }
 }
 

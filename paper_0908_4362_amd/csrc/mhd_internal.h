@@ -24,7 +24,7 @@ struct Ctl {
     double cmax;    // c_max of the current state (from the last reduction)
     double divb;    // result of the last div B reduction
     int status;     // 0 ok, -4 non-finite c_max, -1 invalid input state (latched)
-    int pad;
+    int nparts;     // per-workgroup c_max slots the last producing launch wrote
 };
 
 // Error reporting of the C ABI: record a message for mhd_last_error() and
@@ -34,14 +34,21 @@ int report_hip(hipError_t e, const char* where);
 
 // Grid-wide maxima are reduced in two levels: a producing kernel stores one
 // maximum per workgroup (ordered bit patterns of non-negative doubles) in a
-// parts array, then launch_finish reduces them with one workgroup.
+// parts array, then launch_finish reduces them with one workgroup. A c_max
+// producer of the plain solver also stores its slot count in ctl->nparts, and
+// the finisher of c_max reads the count from there, so a step replayed from a
+// graph reduces exactly the slots the previous producer wrote, whichever
+// launch that was (a fluid sweep of any axis, or the standalone pass).
 size_t reduce_capacity(const Grid& g);   // largest number of parts any launch writes
+// what 0: c_max over ctl->nparts slots (and the dt rule if cfl > 0);
+// what 1: max |div B| over nparts slots into ctl->divb
 hipError_t launch_finish(const unsigned long long* parts, int nparts, int what, double cfl, Ctl* ctl,
-                         hipStream_t s);  // what 0: c_max (and the dt rule if cfl > 0); 1: div B
+                         hipStream_t s);
 
-// Producers (return hipSuccess or the launch error; *nparts = parts written).
+// Producers (return hipSuccess or the launch error). launch_cfl stores its
+// slot count in ctl->nparts on the device; launch_divb returns it in *nparts.
 template <typename T>
-hipError_t launch_cfl(const T* u, const T* b, Grid g, double gamma, unsigned long long* parts, int* nparts,
+hipError_t launch_cfl(const T* u, const T* b, Grid g, double gamma, unsigned long long* parts, Ctl* ctl,
                       hipStream_t s);
 template <typename T>
 hipError_t launch_divb(const T* b, Grid g, unsigned long long* parts, int* nparts, hipStream_t s);
@@ -50,10 +57,10 @@ hipError_t launch_divb(const T* b, Grid g, unsigned long long* parts, int* npart
 // b = (B_x, B_y, B_z), each field-major with N cells per field. A sweep reads
 // the status word and, unless dt >= 0 is given, dt from the control block.
 // With parts non-null the fluid sweep also stores per-workgroup maxima of the
-// CFL speed of the state it writes.
+// CFL speed of the state it writes, and its slot count in ctl->nparts.
 template <typename T>
-hipError_t launch_fluid(int axis, const T* u_in, T* u_out, const T* b, Grid g, double gamma, const Ctl* ctl,
-                        double dt, unsigned long long* parts, int* nparts, hipStream_t s);
+hipError_t launch_fluid(int axis, const T* u_in, T* u_out, const T* b, Grid g, double gamma, Ctl* ctl,
+                        double dt, unsigned long long* parts, hipStream_t s);
 template <typename T>
 hipError_t launch_ct(int axis, const T* u, const T* b_in, T* b_out, Grid g, const Ctl* ctl, double dt,
                      hipStream_t s);

@@ -7,11 +7,11 @@
 #include "mhd_flat_impl.h"
 
 namespace mhd {
-template hipError_t launch_cfl<float>(const float*, const float*, Grid, double, unsigned long long*, int*,
+template hipError_t launch_cfl<float>(const float*, const float*, Grid, double, unsigned long long*, Ctl*,
                                       hipStream_t);
 template hipError_t launch_divb<float>(const float*, Grid, unsigned long long*, int*, hipStream_t);
-template hipError_t launch_fluid<float>(int, const float*, float*, const float*, Grid, double, const Ctl*, double,
-                                        unsigned long long*, int*, hipStream_t);
+template hipError_t launch_fluid<float>(int, const float*, float*, const float*, Grid, double, Ctl*, double,
+                                        unsigned long long*, hipStream_t);
 template hipError_t launch_ct<float>(int, const float*, const float*, float*, Grid, const Ctl*, double,
                                      hipStream_t);
 template hipError_t launch_ct_flat<float>(int, const float*, const float*, float*, Grid, const Ctl*, double,

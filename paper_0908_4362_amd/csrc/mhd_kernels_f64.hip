@@ -7,13 +7,15 @@
 
 namespace mhd {
 namespace {
-// Second level of a grid-wide max: one block reduces nparts per-block maxima;
-// what = 0: c_max into ctl->cmax, then (cfl > 0) the time-step rule;
-// what = 1: max |div B| into ctl->divb.
+// Second level of a grid-wide max: one block reduces the per-block maxima;
+// what = 0: the ctl->nparts slots of the last c_max producer into ctl->cmax,
+// then (cfl > 0) the time-step rule; what = 1: nparts slots of max |div B|
+// into ctl->divb.
 constexpr int FB = 1024;   // threads of the finisher
 __global__ void __launch_bounds__(FB) finish_kernel(const unsigned long long* __restrict__ parts, int nparts,
                                                     int what, double cfl, Ctl* ctl)
 {
+    if (what == 0) nparts = ctl->nparts;
     unsigned long long best = 0ull;
     // unrolled so that each thread has several loads in flight (up to 80
     // slots per thread when an x sweep produced them)
@@ -75,11 +77,11 @@ size_t reduce_capacity(const Grid& g)
     return cap;
 }
 
-template hipError_t launch_cfl<double>(const double*, const double*, Grid, double, unsigned long long*, int*,
+template hipError_t launch_cfl<double>(const double*, const double*, Grid, double, unsigned long long*, Ctl*,
                                        hipStream_t);
 template hipError_t launch_divb<double>(const double*, Grid, unsigned long long*, int*, hipStream_t);
-template hipError_t launch_fluid<double>(int, const double*, double*, const double*, Grid, double, const Ctl*,
-                                         double, unsigned long long*, int*, hipStream_t);
+template hipError_t launch_fluid<double>(int, const double*, double*, const double*, Grid, double, Ctl*,
+                                         double, unsigned long long*, hipStream_t);
 template hipError_t launch_ct<double>(int, const double*, const double*, double*, Grid, const Ctl*, double,
                                       hipStream_t);
 template hipError_t launch_ct_flat<double>(int, const double*, const double*, double*, Grid, const Ctl*, double,

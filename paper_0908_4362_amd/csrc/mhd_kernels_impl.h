@@ -561,13 +561,21 @@ __device__ __forceinline__ void fluid_march_body(const T* __restrict__ uin, T* _
     if constexpr (CFL) block_max_to_part<64 * MW>(best, threadIdx.x + 64 * threadIdx.y, part);
 }
 
+// Slot count of a c_max producer of the plain solver, stored for the
+// finisher by one thread of the launch.
+__device__ __forceinline__ void store_part_count(int* count)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) *count = (int)gridDim.x;
+}
+
 template <typename T, int D, bool CFL>
 __global__ void __launch_bounds__(64 * MW) fluid_march(const T* __restrict__ uin, T* __restrict__ uout,
                                                        const T* __restrict__ bf, Grid g, T gamma,
                                                        const Ctl* __restrict__ ctl, double dt_arg, int chunk,
-                                                       unsigned long long* __restrict__ parts)
+                                                       unsigned long long* __restrict__ parts, int* count)
 {
     const unsigned lb = blockIdx.x;
+    if constexpr (CFL) store_part_count(count);
     fluid_march_body<T, D, CFL>(uin, uout, bf, g, gamma, ctl, dt_arg, chunk, lb, parts + blockIdx.x);
 }
 
@@ -830,8 +838,9 @@ template <typename T, bool CFL>
 __global__ void __launch_bounds__(256) fluid_x_wave(const T* __restrict__ uin, T* __restrict__ uout,
                                                     const T* __restrict__ bf, Grid g, T gamma,
                                                     const Ctl* __restrict__ ctl, double dt_arg,
-                                                    unsigned long long* __restrict__ parts)
+                                                    unsigned long long* __restrict__ parts, int* count)
 {
+    if constexpr (CFL) store_part_count(count);
     fluid_x_body<T, CFL>(uin, uout, bf, g, gamma, ctl, dt_arg, blockIdx.x, parts + blockIdx.x);
 }
 
@@ -968,8 +977,9 @@ __device__ __forceinline__ void cfl_body(const T* __restrict__ u, const T* __res
 
 template <typename T>
 __global__ void __launch_bounds__(RB) cfl_kernel(const T* __restrict__ u, const T* __restrict__ b, Grid g,
-                                                 T gamma, unsigned long long* __restrict__ parts)
+                                                 T gamma, unsigned long long* __restrict__ parts, int* count)
 {
+    store_part_count(count);
     cfl_body<T>(u, b, g, gamma, blockIdx.x, gridDim.x, parts + blockIdx.x);
 }
 
@@ -1049,12 +1059,11 @@ static unsigned march_blocks(const Grid& g, int axis, int chunk, bool xwide)
 }
 
 template <typename T>
-hipError_t launch_cfl(const T* u, const T* b, Grid g, double gamma, unsigned long long* parts, int* nparts,
+hipError_t launch_cfl(const T* u, const T* b, Grid g, double gamma, unsigned long long* parts, Ctl* ctl,
                       hipStream_t s)
 {
     const int nb = reduce_blocks(g);
-    hipLaunchKernelGGL((cfl_kernel<T>), dim3(nb), dim3(RB), 0, s, u, b, g, (T)gamma, parts);
-    *nparts = nb;
+    hipLaunchKernelGGL((cfl_kernel<T>), dim3(nb), dim3(RB), 0, s, u, b, g, (T)gamma, parts, &ctl->nparts);
     return hipGetLastError();
 }
 
@@ -1068,36 +1077,35 @@ hipError_t launch_divb(const T* b, Grid g, unsigned long long* parts, int* npart
 }
 
 template <typename T, bool CFL>
-static void fluid_launch(int axis, const T* u_in, T* u_out, const T* b, Grid g, double gamma, const Ctl* ctl,
-                         double dt, unsigned long long* parts, int* nparts, hipStream_t s)
+static void fluid_launch(int axis, const T* u_in, T* u_out, const T* b, Grid g, double gamma, Ctl* ctl,
+                         double dt, unsigned long long* parts, hipStream_t s)
 {
-    unsigned nb;
+    int* count = CFL ? &ctl->nparts : nullptr;
     if (axis == 0) {
-        nb = x_wave_blocks(g);
+        const unsigned nb = x_wave_blocks(g);
         hipLaunchKernelGGL((fluid_x_wave<T, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
-                           parts);
+                           parts, count);
     } else {
         const int chunk = march_chunk(g, axis, GF, kFluidMarchWaves, true);
-        nb = march_blocks(g, axis, chunk, kMarchXWide<T, false>);
+        const unsigned nb = march_blocks(g, axis, chunk, kMarchXWide<T, false>);
         const dim3 block(64, MW);
         if (axis == 1)
             hipLaunchKernelGGL((fluid_march<T, 1, CFL>), dim3(nb), block, 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
-                               chunk, parts);
+                               chunk, parts, count);
         else
             hipLaunchKernelGGL((fluid_march<T, 2, CFL>), dim3(nb), block, 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
-                               chunk, parts);
+                               chunk, parts, count);
     }
-    if (nparts) *nparts = (int)nb;
 }
 
 template <typename T>
-hipError_t launch_fluid(int axis, const T* u_in, T* u_out, const T* b, Grid g, double gamma, const Ctl* ctl,
-                        double dt, unsigned long long* parts, int* nparts, hipStream_t s)
+hipError_t launch_fluid(int axis, const T* u_in, T* u_out, const T* b, Grid g, double gamma, Ctl* ctl,
+                        double dt, unsigned long long* parts, hipStream_t s)
 {
     if (parts)
-        fluid_launch<T, true>(axis, u_in, u_out, b, g, gamma, ctl, dt, parts, nparts, s);
+        fluid_launch<T, true>(axis, u_in, u_out, b, g, gamma, ctl, dt, parts, s);
     else
-        fluid_launch<T, false>(axis, u_in, u_out, b, g, gamma, ctl, dt, nullptr, nullptr, s);
+        fluid_launch<T, false>(axis, u_in, u_out, b, g, gamma, ctl, dt, nullptr, s);
     return hipGetLastError();
 }
 

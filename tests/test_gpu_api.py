@@ -300,3 +300,70 @@ def test_stream_switch_keeps_the_handle_ordered(B):
         ref.set_state(s)
         ref.step(5)
         assert np.array_equal(end, ref.get_state())
+
+
+def _hot_corner_state(nx, ny, nz, seed):
+    """Random smooth state with its fastest cells in a small block near the
+    far corner (high j and k): their c_max slot lies in the upper part of
+    every producer's slot range, so a finisher that reduces too few slots
+    (or stale ones) gets another c_max and another dt."""
+    s = P.random_smooth(nx, ny, nz, seed=seed)
+    k0, j0, i0 = nz - 5, ny - 4, nx - 6
+    blk = (slice(k0, k0 + 3), slice(j0, j0 + 3), slice(i0, i0 + 3))
+    rho, mx = s[0][blk], s[1][blk]
+    dm = 1.5 * rho
+    s[4][blk] += ((mx + dm) ** 2 - mx ** 2) / (2.0 * rho)   # same pressure, faster flow
+    s[1][blk] += dm
+    return s
+
+
+def test_graph_replay_reduces_the_slots_of_the_last_producer(B):
+    """Steps replayed from graphs after mhd_cmax and after mhd_set_time moves
+    the sweep order: the c_max slots then come from a producer other than the
+    one the graph was captured after (the standalone pass, or the last fluid
+    sweep of another sweep order), each writing another number of slots. The
+    finisher must reduce exactly those, so the sequence with graphs equals
+    the one without, bit for bit, and the FP64 run equals the oracle's
+    (Sec. 3 eq. equat_CFL: dt from c_max of the state being stepped)."""
+    import torch
+
+    import oracle
+
+    nx, ny, nz = 64, 48, 40
+    s0 = _hot_corner_state(nx, ny, nz, P.MASTER_SEED + 49)
+    stream = torch.cuda.Stream()
+    cfl = 0.7
+    note("graph replay after mhd_cmax and mhd_set_time")
+    results = {}
+    for dtype in (B.MHD_F64, B.MHD_F32):
+        for graphs in (True, False):
+            seq = []
+            with B.Solver(nx, ny, nz, H.GAMMA53, 0, dtype) as sv:
+                B.mhd_set_stream(sv.h, stream)
+                B.mhd_set_graphs(sv.h, graphs)
+                sv.set_state(s0)
+                sv.step(4, cfl)
+                seq.append((sv.get_state(), sv.time()))
+                seq.append(B.mhd_cmax(sv.h))
+                sv.step(4, cfl)
+                seq.append((sv.get_state(), sv.time()))
+                t, st = sv.time()
+                B.mhd_set_time(sv.h, t, st + 1)
+                sv.step(4, cfl)
+                seq.append((sv.get_state(), sv.time()))
+            results[(dtype, graphs)] = seq
+        for a, b in zip(results[(dtype, True)], results[(dtype, False)]):
+            if isinstance(a, tuple):
+                assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+            else:
+                assert a == b
+    g = oracle.Grid(nx, ny, nz, H.GAMMA53, 0)
+    w1, t1, s1 = oracle.run(g, s0, 4, cfl)
+    w2, t2, s2 = oracle.run(g, w1, 4, cfl, t=t1, step=s1)
+    w3, t3, _ = oracle.run(g, w2, 4, cfl, t=t2, step=s2 + 1)
+    got = results[(B.MHD_F64, True)]
+    assert got[1] == oracle.cmax(g, w1)
+    for (state, (t, st)), (want, tw, sw) in zip([got[0], got[2], got[3]],
+                                                [(w1, t1, 4), (w2, t2, 8), (w3, t3, 13)]):
+        assert st == sw and t == tw, (st, sw, t, tw)
+        assert np.array_equal(state, want)

@@ -376,3 +376,53 @@ def test_long_blast_run_conserves_and_keeps_divb(B, dtype):
         assert abs(out[f].sum() - s64[f].sum()) <= eps * scale, (f, out[f].sum(), s64[f].sum())
     bmax = np.abs(out[5:]).max()
     assert dmax <= (1e-13 if dtype == 1 else 3e-5) * bmax, dmax
+
+
+# --------------------------------------------------------------- div B reduction
+
+DIVB_SHAPES = [(33, 26, 20), (40, 30, 1), (1, 25, 21), (17, 1, 1), (1, 1, 23), (70, 3, 2), (24, 100, 90)]
+
+
+def planted_divb_state(shape, seed):
+    """Random smooth state whose face fields carry random perturbations (a
+    discrete divergence of about 1e-3 in every cell) plus one large planted
+    transverse value on the upper face layer of each axis longer than one cell:
+    under outflow boundaries the two cells it touches are edge cells, left out
+    of the maximum; under periodic ones they hold the largest divergence."""
+    nx, ny, nz = shape
+    s = P.random_smooth(nx, ny, nz, seed=seed)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s[5:] += 1e-3 * rng.standard_normal(s[5:].shape)
+    if ny > 1:
+        s[5][nz // 2, ny - 1, nx // 2] += 0.5      # B_x on the top y layer
+    if nz > 1:
+        s[6][nz - 1, ny // 3, nx // 3] -= 0.75     # B_y on the top z layer
+    if nx > 1:
+        s[7][nz // 4, ny // 2, nx - 1] += 1.25     # B_z on the top x layer
+    return s
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("shape", DIVB_SHAPES)
+def test_divb_max_matches_the_oracle(B, shape, bc):
+    """mhd_divb_max against the oracle's brute-force maximum of the
+    face-difference divergence (Sec. 3: div B of the face field, which the
+    constrained-transport update keeps at round-off) on states where it is
+    far from zero: FP64 bit for bit, FP32 (the oracle fed the same rounded
+    state) to 1e-6 relative."""
+    import oracle
+
+    nx, ny, nz = shape
+    s = planted_divb_state(shape, P.MASTER_SEED + 300 + sum(shape))
+    note("div B parity %s bc %d" % (shape, bc))
+    for dtype in (B.MHD_F64, B.MHD_F32):
+        with B.Solver(nx, ny, nz, H.GAMMA53, bc, dtype) as sv:
+            sv.set_state(s)
+            got = sv.divb_max()
+            fed = sv.get_state().astype(np.float64)
+        want = oracle.divb_max(oracle.Grid(nx, ny, nz, H.GAMMA53, bc), fed)
+        assert want > 1e-3
+        if dtype == B.MHD_F64:
+            assert got == want, (got, want)
+        else:
+            assert abs(got - want) <= 1e-6 * want, (got, want)
