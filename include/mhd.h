@@ -62,9 +62,13 @@ enum { MHD_F32 = 0, MHD_F64 = 1 };
  * all; sizes need not be powers of two), adiabatic index gamma > 1, boundary
  * condition bc applied on
  * every axis (periodic wrap, or outflow = zero-gradient copy of cell and face
- * values beyond the edge) and arithmetic type dtype. The handle owns its
- * device memory: two ping-pong copies of the state plus a few scalars. The
- * state starts undefined; call mhd_set_state before stepping. */
+ * values beyond the edge) and arithmetic type dtype. The paper's program
+ * works on a regular Cartesian grid in single or double precision and keeps
+ * the eight components in eight arrays in device memory (Sec. 4, its opening
+ * and Sec. 4.1); this call is the set-up of steps 1-2 of its program flow
+ * (Sec. 4.2). The handle owns its device memory: two ping-pong copies of the
+ * state plus a few scalars. The state starts undefined; call mhd_set_state
+ * before stepping. */
 int mhd_create(int nx, int ny, int nz, double gamma, int bc, int dtype, mhd_t** out);
 
 /* Release the handle and its device memory (null is accepted). */
@@ -82,7 +86,9 @@ int mhd_set_stream(mhd_t* h, void* stream);
  * host cost that dominates small grids. Results are identical either way. */
 int mhd_set_graphs(mhd_t* h, int enable);
 
-/* Copy a state in (layout above) from host memory or from device memory;
+/* Copy a state in (layout above) from host memory or from device memory
+ * (step 3 of the program flow of Sec. 4.2: the initial u and face B to
+ * device memory; with t set to 0 as in step 2);
  * resets t = 0 and the step counter s = 0, then checks it on the device and
  * returns MHD_ERR_ARG if a value is not finite or a density is not positive
  * (the handle then refuses to step, with MHD_ERR_ARG, until a valid state is
@@ -92,7 +98,8 @@ int mhd_set_state(mhd_t* h, const void* host_state);
 int mhd_set_state_device(mhd_t* h, const void* dev_state);
 
 /* Copy the current state out (layout above) to host memory (synchronises the
- * stream) or to device memory (asynchronous on the handle's stream). */
+ * stream) or to device memory (asynchronous on the handle's stream): step 10
+ * of the program flow of Sec. 4.2 (read u and B back). */
 int mhd_get_state(mhd_t* h, void* host_state);
 int mhd_get_state_device(mhd_t* h, void* dev_state);
 
@@ -110,9 +117,12 @@ int mhd_get_state_device(mhd_t* h, void* dev_state);
  * last is one mhd_set_state rejected. */
 int mhd_step(mhd_t* h, int n, double cfl);
 
-/* max over cells of |sum_d (B_d(c + e_d) - B_d(c))| in unit cells; with
- * outflow boundaries only cells whose upper faces are stored are counted
- * (axes of size 1 contribute nothing). Synchronises the stream. */
+/* max over cells of |sum_d (B_d(c + e_d) - B_d(c))| in unit cells: the
+ * discrete div B of the face field of eq. equat_b, which the constrained
+ * transport of Sec. 3 keeps at machine precision (the constraint div B = 0
+ * stated with the MHD equations, Sec. 3). With outflow boundaries only cells
+ * whose upper faces are stored are counted (axes of size 1 contribute
+ * nothing). Synchronises the stream. */
 int mhd_divb_max(mhd_t* h, double* out);
 
 /* Simulation time and step counter (s mod 3 selects the sweep order). */
@@ -183,7 +193,7 @@ size_t mhd_workspace_bytes(int nx, int ny, int nz, int dtype);
 int mhd_bind_workspace(mhd_t* h, void* dev, size_t bytes);
 
 /* Headless diagnostics: the derived fields one would render (the paper shows
- * density, gas pressure and field images, Sec. 4.4 and Sec. 5), computed on
+ * density, gas pressure and field images, Sec. 5 and Sec. 8), computed on
  * the device from the current state with the centred field of eq. equat_b
  * averaged from the two faces of each cell:
  *   MHD_D_PRESSURE           p = (gamma - 1)(E - rho v^2 / 2 - b^2 / 2)

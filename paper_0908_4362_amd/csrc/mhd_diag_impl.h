@@ -1,5 +1,5 @@
 // Derived fields of a state for headless diagnostics, in place of the paper's
-// on-screen rendering of the density, pressure and field (Sec. 4.4): gas
+// on-screen rendering of the density, pressure and field (Sec. 8): gas
 // pressure, magnetic pressure, speed, CFL speed and the cell divergence of B,
 // for the whole grid or for one plane of it; and the check of an input state
 // (every value finite, density positive).

@@ -9,7 +9,7 @@ namespace {
 
 // Every cell of an EMF pencil along d is the same cell, so the marching
 // pipeline (smoothing, first-order upwind EMF, half step, limited slope,
-// second-order EMF; Sec. 3.2, Alg. 2) sees a constant input and, after the
+// second-order EMF; Sec. 3 and Alg. 2) sees a constant input and, after the
 // eight cells of its latency (its 2 x 4 ghost cells cover them), holds a fixed
 // point: smoothed velocity V = (v + 2v + v) / 4, first- and second-order EMFs
 // Q = V B (every difference along the pencil an exact zero, so the half step
