@@ -2,7 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY. This is the slow, serial, FP64 reference the GPU
 library is checked against (plain C in ``mhd_oracle.c``, loaded here through
-ctypes). Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline``
+ctypes; ``set_threads(n)`` switches to the OpenMP build of the same source,
+which shares the pencils of each sweep among n threads and gives the same
+bits). Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline``
 leg of ``bench.py`` may import it; the GPU library never does.
 
 States are numpy float64 arrays of shape (8, nz, ny, nx): fields rho, m_x,
@@ -20,23 +22,39 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mhd_oracle.c")
 _SO = os.path.join(_HERE, "liborc_mhd.so")
-_lib = None
+_SO_OMP = os.path.join(_HERE, "liborc_mhd_omp.so")
+_libs = {}
+_threads = 1
 
 PERIODIC, OUTFLOW = 0, 1
 
+# -O3 without FMA contraction or fast-math: every expression rounds as written
+_CFLAGS = ["-O3", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def _compile(out, extra):
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", *_CFLAGS, *extra, "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, out)
+
 
 def build(force: bool = False) -> str:
-    """Compile the oracle (serial, -O2, no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < max(
-        os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "mhd_oracle.h"))
-    ):
-        tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-             "-o", tmp, _SRC, "-lm"]
-        )
-        os.replace(tmp, _SO)
+    """Compile the oracle: the serial library and the OpenMP one (the same
+    source with its pencil loops shared among threads, same bits)."""
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "mhd_oracle.h")))
+    for so, extra in ((_SO, []), (_SO_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(so) or os.path.getmtime(so) < newest:
+            _compile(so, extra)
     return _SO
+
+
+def set_threads(n: int) -> int:
+    """Run the oracle on n threads (1: the serial build; more: the OpenMP
+    build with n threads). Returns the thread count in use."""
+    global _threads
+    _threads = max(1, int(n))
+    lib = _load()
+    return int(lib.orc_set_threads(_threads)) if _threads > 1 else 1
 
 
 class _Grid(ctypes.Structure):
@@ -44,10 +62,11 @@ class _Grid(ctypes.Structure):
 
 
 def _load():
-    global _lib
-    if _lib is None:
+    key = "omp" if _threads > 1 else "serial"
+    lib = _libs.get(key)
+    if lib is None:
         build()
-        lib = ctypes.CDLL(_SO)
+        lib = ctypes.CDLL(_SO_OMP if key == "omp" else _SO)
         dp = ctypes.POINTER(ctypes.c_double)
         gp = ctypes.POINTER(_Grid)
         lib.orc_vanleer.restype = ctypes.c_double
@@ -69,8 +88,10 @@ def _load():
                                  ctypes.POINTER(ctypes.c_longlong)]
         lib.orc_divb_max.restype = ctypes.c_double
         lib.orc_divb_max.argtypes = [gp, dp]
-        _lib = lib
-    return _lib
+        lib.orc_set_threads.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        _libs[key] = lib
+    return lib
 
 
 def _ptr(a: np.ndarray):

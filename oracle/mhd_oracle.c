@@ -7,6 +7,11 @@
  * baseline of the benchmark; never by the GPU library. Build with
  * -ffp-contract=off and without fast-math.
  *
+ * Built with -fopenmp, the independent pencils of a sweep (and the cells of
+ * the two maxima) are shared among threads; each pencil's arithmetic is the
+ * same code in the same order, and maxima are exact, so the threaded build
+ * gives the serial build's bits. Without -fopenmp the pragmas are ignored.
+ *
  * Every derived quantity (centred field, face velocity, flux, mover, limiter
  * slope, EMF) at any index, inside the grid or beyond its edge, is computed
  * from the boundary-mapped primary state (rho, m, E, face B); a derived
@@ -18,6 +23,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 enum { RHO = 0, MX = 1, EN = 4, BX = 5 };
 #define NF 8
@@ -96,87 +104,128 @@ static double slope(double qm, double q0, double qp)
     return orc_vanleer((q0 - qm) / 2.0, (qp - q0) / 2.0);
 }
 
-void orc_fluid_sweep(const orc_grid* g, const double* in, double* out, int d, double dt)
+/* out = in for a whole state (the OpenMP build copies in parallel chunks). */
+static void copy_state(const orc_grid* g, const double* in, double* out)
+{
+    const long total = NF * ncell(g);
+    const long chunk = 1L << 16;
+    const long nchunks = (total + chunk - 1) / chunk;
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < nchunks; c++) {
+        const long lo = c * chunk, hi = lo + chunk < total ? lo + chunk : total;
+        memcpy(out + lo, in + lo, sizeof(double) * (hi - lo));
+    }
+}
+
+/* Work arrays of one extended pencil of the fluid sweep (index m + GF for m
+ * in [-GF, n + GF)). */
+typedef struct {
+    double *u, *b, *r, *l, *ph1, *uh, *rh, *lh, *sr, *sl, *ph2;
+} fluid_work;
+
+static void fluid_work_alloc(fluid_work* w, int W)
+{
+    w->u = malloc(sizeof(double) * 5 * W);
+    w->b = malloc(sizeof(double) * 3 * W);
+    w->r = malloc(sizeof(double) * 5 * W);
+    w->l = malloc(sizeof(double) * 5 * W);
+    w->ph1 = malloc(sizeof(double) * 5 * W);
+    w->uh = malloc(sizeof(double) * 5 * W);
+    w->rh = malloc(sizeof(double) * 5 * W);
+    w->lh = malloc(sizeof(double) * 5 * W);
+    w->sr = malloc(sizeof(double) * 5 * W);
+    w->sl = malloc(sizeof(double) * 5 * W);
+    w->ph2 = malloc(sizeof(double) * 5 * W);
+}
+
+static void fluid_work_free(fluid_work* w)
+{
+    free(w->u); free(w->b); free(w->r); free(w->l); free(w->ph1); free(w->uh);
+    free(w->rh); free(w->lh); free(w->sr); free(w->sl); free(w->ph2);
+}
+
+/* fluid_d on the d-pencil with transverse coordinates (ae, af). */
+static void fluid_pencil(const orc_grid* g, const double* in, double* out, int d, double dt, int ae, int af,
+                         fluid_work* w)
 {
     const int e = (d + 1) % 3, f = (d + 2) % 3;
     const int n = g->n[d];
     const long N = ncell(g);
-    const int W = n + 2 * GF;
-    memcpy(out, in, sizeof(double) * NF * N);
-
-    /* work arrays over the extended pencil, index m + GF for m in [-GF, n+GF) */
-    double* u = malloc(sizeof(double) * 5 * W);
-    double* b = malloc(sizeof(double) * 3 * W);
-    double* r = malloc(sizeof(double) * 5 * W);
-    double* l = malloc(sizeof(double) * 5 * W);
-    double* ph1 = malloc(sizeof(double) * 5 * W);
-    double* uh = malloc(sizeof(double) * 5 * W);
-    double* rh = malloc(sizeof(double) * 5 * W);
-    double* lh = malloc(sizeof(double) * 5 * W);
-    double* sr = malloc(sizeof(double) * 5 * W);
-    double* sl = malloc(sizeof(double) * 5 * W);
-    double* ph2 = malloc(sizeof(double) * 5 * W);
+    double *u = w->u, *b = w->b, *r = w->r, *l = w->l, *ph1 = w->ph1, *uh = w->uh;
+    double *rh = w->rh, *lh = w->lh, *sr = w->sr, *sl = w->sl, *ph2 = w->ph2;
 #define AT(a, m) ((a) + 5 * ((m) + GF))
 
     const int mom[3] = {MX + d, MX + e, MX + f};
     const int bf[3] = {BX + d, BX + e, BX + f};
     const int ax[3] = {d, e, f};
 
-    for (int af = 0; af < g->n[f]; af++)
-        for (int ae = 0; ae < g->n[e]; ae++) {
-            /* load the extended pencil: conserved u (normal momentum second) and
-             * the cell-centred field, the mean of the two faces (Alg. 1 step 3). */
-            for (int m = -GF; m < n + GF; m++) {
-                int c[3];
-                c[d] = m; c[e] = ae; c[f] = af;
-                long i0 = lin(g, c);
-                double* uu = AT(u, m);
-                uu[0] = fld(g, in, RHO)[i0];
-                uu[1] = fld(g, in, mom[0])[i0];
-                uu[2] = fld(g, in, mom[1])[i0];
-                uu[3] = fld(g, in, mom[2])[i0];
-                uu[4] = fld(g, in, EN)[i0];
-                double* bb = b + 3 * (m + GF);
-                for (int q = 0; q < 3; q++) {
-                    int cp[3] = {c[0], c[1], c[2]};
-                    cp[ax[q]] += 1;
-                    bb[q] = 0.5 * (fld(g, in, bf[q])[i0] + fld(g, in, bf[q])[lin(g, cp)]);
-                }
-            }
-            /* stage 1: first-order upwind fluxes from the movers of u^t
-             * (eq. Delta_u_half): F_{m+1/2} = r_m - l_{m+1}. */
-            for (int m = -GF; m < n + GF; m++) movers(AT(u, m), b + 3 * (m + GF), g->gamma, AT(r, m), AT(l, m));
-            for (int m = -GF; m < n + GF - 1; m++)
-                for (int q = 0; q < 5; q++) AT(ph1, m)[q] = AT(r, m)[q] - AT(l, m + 1)[q];
-            for (int m = -GF + 1; m < n + GF - 1; m++)
-                for (int q = 0; q < 5; q++)
-                    AT(uh, m)[q] = AT(u, m)[q] - (dt / 2.0) * (AT(ph1, m)[q] - AT(ph1, m - 1)[q]);
-            /* stage 2: movers of u^{t+dt/2} (Alg. 1 step 7, same field), MUSCL
-             * corrections with the van Leer limiter, and the full update from
-             * u^t (eq. Delta_u_full). */
-            for (int m = -GF + 1; m < n + GF - 1; m++)
-                movers(AT(uh, m), b + 3 * (m + GF), g->gamma, AT(rh, m), AT(lh, m));
-            for (int m = -GF + 2; m < n + GF - 2; m++)
-                for (int q = 0; q < 5; q++) {
-                    AT(sr, m)[q] = slope(AT(rh, m - 1)[q], AT(rh, m)[q], AT(rh, m + 1)[q]);
-                    AT(sl, m)[q] = slope(AT(lh, m - 1)[q], AT(lh, m)[q], AT(lh, m + 1)[q]);
-                }
-            /* right mover upwinded from cell m, left mover from cell m+1 */
-            for (int m = -1; m < n; m++)
-                for (int q = 0; q < 5; q++)
-                    AT(ph2, m)[q] = (AT(rh, m)[q] + AT(sr, m)[q]) - (AT(lh, m + 1)[q] - AT(sl, m + 1)[q]);
-            for (int m = 0; m < n; m++) {
-                int c[3];
-                c[d] = m; c[e] = ae; c[f] = af;
-                long i0 = lin(g, c);
-                const int dst[5] = {RHO, mom[0], mom[1], mom[2], EN};
-                for (int q = 0; q < 5; q++)
-                    out[(long)dst[q] * N + i0] = AT(u, m)[q] - dt * (AT(ph2, m)[q] - AT(ph2, m - 1)[q]);
-            }
+    /* load the extended pencil: conserved u (normal momentum second) and
+     * the cell-centred field, the mean of the two faces (Alg. 1 step 3). */
+    for (int m = -GF; m < n + GF; m++) {
+        int c[3];
+        c[d] = m; c[e] = ae; c[f] = af;
+        long i0 = lin(g, c);
+        double* uu = AT(u, m);
+        uu[0] = fld(g, in, RHO)[i0];
+        uu[1] = fld(g, in, mom[0])[i0];
+        uu[2] = fld(g, in, mom[1])[i0];
+        uu[3] = fld(g, in, mom[2])[i0];
+        uu[4] = fld(g, in, EN)[i0];
+        double* bb = b + 3 * (m + GF);
+        for (int q = 0; q < 3; q++) {
+            int cp[3] = {c[0], c[1], c[2]};
+            cp[ax[q]] += 1;
+            bb[q] = 0.5 * (fld(g, in, bf[q])[i0] + fld(g, in, bf[q])[lin(g, cp)]);
         }
+    }
+    /* stage 1: first-order upwind fluxes from the movers of u^t
+     * (eq. Delta_u_half): F_{m+1/2} = r_m - l_{m+1}. */
+    for (int m = -GF; m < n + GF; m++) movers(AT(u, m), b + 3 * (m + GF), g->gamma, AT(r, m), AT(l, m));
+    for (int m = -GF; m < n + GF - 1; m++)
+        for (int q = 0; q < 5; q++) AT(ph1, m)[q] = AT(r, m)[q] - AT(l, m + 1)[q];
+    for (int m = -GF + 1; m < n + GF - 1; m++)
+        for (int q = 0; q < 5; q++)
+            AT(uh, m)[q] = AT(u, m)[q] - (dt / 2.0) * (AT(ph1, m)[q] - AT(ph1, m - 1)[q]);
+    /* stage 2: movers of u^{t+dt/2} (Alg. 1 step 7, same field), MUSCL
+     * corrections with the van Leer limiter, and the full update from
+     * u^t (eq. Delta_u_full). */
+    for (int m = -GF + 1; m < n + GF - 1; m++)
+        movers(AT(uh, m), b + 3 * (m + GF), g->gamma, AT(rh, m), AT(lh, m));
+    for (int m = -GF + 2; m < n + GF - 2; m++)
+        for (int q = 0; q < 5; q++) {
+            AT(sr, m)[q] = slope(AT(rh, m - 1)[q], AT(rh, m)[q], AT(rh, m + 1)[q]);
+            AT(sl, m)[q] = slope(AT(lh, m - 1)[q], AT(lh, m)[q], AT(lh, m + 1)[q]);
+        }
+    /* right mover upwinded from cell m, left mover from cell m+1 */
+    for (int m = -1; m < n; m++)
+        for (int q = 0; q < 5; q++)
+            AT(ph2, m)[q] = (AT(rh, m)[q] + AT(sr, m)[q]) - (AT(lh, m + 1)[q] - AT(sl, m + 1)[q]);
+    for (int m = 0; m < n; m++) {
+        int c[3];
+        c[d] = m; c[e] = ae; c[f] = af;
+        long i0 = lin(g, c);
+        const int dst[5] = {RHO, mom[0], mom[1], mom[2], EN};
+        for (int q = 0; q < 5; q++)
+            out[(long)dst[q] * N + i0] = AT(u, m)[q] - dt * (AT(ph2, m)[q] - AT(ph2, m - 1)[q]);
+    }
 #undef AT
-    free(u); free(b); free(r); free(l); free(ph1); free(uh);
-    free(rh); free(lh); free(sr); free(sl); free(ph2);
+}
+
+void orc_fluid_sweep(const orc_grid* g, const double* in, double* out, int d, double dt)
+{
+    const int e = (d + 1) % 3, f = (d + 2) % 3;
+    const long N = ncell(g);
+    const long npen = (long)g->n[e] * g->n[f];
+    copy_state(g, in, out);
+#pragma omp parallel
+    {
+        fluid_work w;
+        fluid_work_alloc(&w, g->n[d] + 2 * GF);
+#pragma omp for schedule(static)
+        for (long p = 0; p < npen; p++)
+            fluid_pencil(g, in, out, d, dt, (int)(p % g->n[e]), (int)(p / g->n[e]), &w);
+        fluid_work_free(&w);
+    }
 }
 
 /*
@@ -235,16 +284,18 @@ static void emf_pencil(const orc_grid* g, const double* s, int d, int k, const i
     free(vhat); free(bk); free(v); free(q); free(vh); free(g1); free(bh); free(qh); free(sq);
 }
 
-void orc_ct_sweep(const orc_grid* g, const double* in, double* out, int d, double dt)
+/* B_{e->d} and B_{f->d} on the d-pencil with transverse coordinates (ae, af);
+ * G holds four EMF arrays of n + 1 values. */
+static void ct_pencil(const orc_grid* g, const double* in, double* out, int d, double dt, int ae, int af,
+                      double* G)
 {
     const int e = (d + 1) % 3, f = (d + 2) % 3;
     const int n = g->n[d];
     const long N = ncell(g);
-    memcpy(out, in, sizeof(double) * NF * N);
-    double* Ge0 = malloc(sizeof(double) * (n + 1));
-    double* Ge1 = malloc(sizeof(double) * (n + 1));
-    double* Gf0 = malloc(sizeof(double) * (n + 1));
-    double* Gf1 = malloc(sizeof(double) * (n + 1));
+    double* Ge0 = G;
+    double* Ge1 = G + (n + 1);
+    double* Gf0 = G + 2 * (n + 1);
+    double* Gf1 = G + 3 * (n + 1);
     const double* Bd = fld(g, in, BX + d);
     const double* Be = fld(g, in, BX + e);
     const double* Bf = fld(g, in, BX + f);
@@ -252,37 +303,51 @@ void orc_ct_sweep(const orc_grid* g, const double* in, double* out, int d, doubl
     double* oBe = out + (long)(BX + e) * N;
     double* oBf = out + (long)(BX + f) * N;
 
-    for (int af = 0; af < g->n[f]; af++)
-        for (int ae = 0; ae < g->n[e]; ae++) {
-            int c0[3];
-            c0[d] = 0; c0[e] = ae; c0[f] = af;
-            int c1[3] = {c0[0], c0[1], c0[2]};
-            c1[e] += 1;
-            int c2[3] = {c0[0], c0[1], c0[2]};
-            c2[f] += 1;
-            /* B_{e->d} and B_{f->d}: both read the same (frozen) fluid state */
-            emf_pencil(g, in, d, e, c0, dt, Ge0);
-            emf_pencil(g, in, d, e, c1, dt, Ge1);
-            emf_pencil(g, in, d, f, c0, dt, Gf0);
-            emf_pencil(g, in, d, f, c2, dt, Gf1);
-            for (int m = 0; m < n; m++) {
-                int c[3];
-                c[d] = m; c[e] = ae; c[f] = af;
-                long i0 = lin(g, c);
-                /* advection of the transverse components: -dt d_d(v_d B_k) */
-                oBe[i0] = Be[i0] - dt * (Ge0[m + 1] - Ge0[m]);
-                oBf[i0] = Bf[i0] - dt * (Gf0[m + 1] - Gf0[m]);
-                /* constraint: the same EMFs update B_d on face m (between
-                 * cells m-1 and m), +dt d_k(v_d B_k); e contribution first. */
-                oBd[i0] = (Bd[i0] + dt * (Ge1[m] - Ge0[m])) + dt * (Gf1[m] - Gf0[m]);
-            }
-        }
-    free(Ge0); free(Ge1); free(Gf0); free(Gf1);
+    int c0[3];
+    c0[d] = 0; c0[e] = ae; c0[f] = af;
+    int c1[3] = {c0[0], c0[1], c0[2]};
+    c1[e] += 1;
+    int c2[3] = {c0[0], c0[1], c0[2]};
+    c2[f] += 1;
+    /* B_{e->d} and B_{f->d}: both read the same (frozen) fluid state */
+    emf_pencil(g, in, d, e, c0, dt, Ge0);
+    emf_pencil(g, in, d, e, c1, dt, Ge1);
+    emf_pencil(g, in, d, f, c0, dt, Gf0);
+    emf_pencil(g, in, d, f, c2, dt, Gf1);
+    for (int m = 0; m < n; m++) {
+        int c[3];
+        c[d] = m; c[e] = ae; c[f] = af;
+        long i0 = lin(g, c);
+        /* advection of the transverse components: -dt d_d(v_d B_k) */
+        oBe[i0] = Be[i0] - dt * (Ge0[m + 1] - Ge0[m]);
+        oBf[i0] = Bf[i0] - dt * (Gf0[m + 1] - Gf0[m]);
+        /* constraint: the same EMFs update B_d on face m (between
+         * cells m-1 and m), +dt d_k(v_d B_k); e contribution first. */
+        oBd[i0] = (Bd[i0] + dt * (Ge1[m] - Ge0[m])) + dt * (Gf1[m] - Gf0[m]);
+    }
+}
+
+void orc_ct_sweep(const orc_grid* g, const double* in, double* out, int d, double dt)
+{
+    const int e = (d + 1) % 3, f = (d + 2) % 3;
+    const int n = g->n[d];
+    const long N = ncell(g);
+    const long npen = (long)g->n[e] * g->n[f];
+    copy_state(g, in, out);
+#pragma omp parallel
+    {
+        double* G = malloc(sizeof(double) * 4 * (n + 1));
+#pragma omp for schedule(static)
+        for (long p = 0; p < npen; p++) ct_pencil(g, in, out, d, dt, (int)(p % g->n[e]), (int)(p / g->n[e]), G);
+        free(G);
+    }
 }
 
 double orc_cmax(const orc_grid* g, const double* s)
 {
     double cmax = 0.0;
+    int saw_nan = 0;
+#pragma omp parallel for schedule(static) reduction(max : cmax) reduction(| : saw_nan)
     for (int k = 0; k < g->n[2]; k++)
         for (int j = 0; j < g->n[1]; j++)
             for (int i = 0; i < g->n[0]; i++) {
@@ -302,10 +367,10 @@ double orc_cmax(const orc_grid* g, const double* s)
                 /* eq. equat_CFL: largest |v| component plus the fast speed bound */
                 double vm = fmax(fabs(v[0]), fmax(fabs(v[1]), fabs(v[2])));
                 double cc = vm + sqrt(fabs(g->gamma * p + bb) / rho);
-                if (isnan(cc)) return NAN;
-                if (cc > cmax) cmax = cc;
+                if (isnan(cc)) saw_nan = 1;
+                else if (cc > cmax) cmax = cc;
             }
-    return cmax;
+    return saw_nan ? NAN : cmax;
 }
 
 int orc_dt(double cmax, double cfl, double t, double t_stop, double* dt, double* t_new)
@@ -364,6 +429,7 @@ int orc_step(const orc_grid* g, double* s, double cfl, double t_stop, double* t,
 double orc_divb_max(const orc_grid* g, const double* s)
 {
     double mx = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : mx)
     for (int k = 0; k < g->n[2]; k++)
         for (int j = 0; j < g->n[1]; j++)
             for (int i = 0; i < g->n[0]; i++) {
@@ -383,4 +449,15 @@ double orc_divb_max(const orc_grid* g, const double* s)
                 if (fabs(div) > mx) mx = fabs(div);
             }
     return mx;
+}
+
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

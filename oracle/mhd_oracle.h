@@ -4,7 +4,8 @@
  * graphics processing units with CUDA", Sec. 3).
  *
  * TEST INFRASTRUCTURE ONLY. This code is the slow, serial, FP64 reference that
- * the GPU path is checked against. Only the test suite, the smoke check and the
+ * the GPU path is checked against (a build with -fopenmp shares the pencils
+ * of each sweep among threads and gives the same bits). Only the test suite, the smoke check and the
  * CPU-baseline leg of the benchmark may load it. It shares no code, header,
  * table or helper with the GPU library.
  *
@@ -59,6 +60,10 @@ int orc_step(const orc_grid* g, double* s, double cfl, double t_stop, double* t,
 
 /* max |div B| over cells whose faces are all stored (all cells if periodic). */
 double orc_divb_max(const orc_grid* g, const double* s);
+
+/* Threads of the OpenMP build (n > 0 sets them); returns the count in use,
+ * 1 for the serial build. Results do not depend on it. */
+int orc_set_threads(int n);
 
 #ifdef __cplusplus
 }
