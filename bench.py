@@ -126,6 +126,17 @@ def measured_traffic(prec, kind, n):
     return table.get((prec, kind))
 
 
+def step_roofline(sec_per_step, ncell, esize):
+    """The whole step against HBM: the path's minimum of STEP_WORDS words per cell (every directional
+    operator reads and writes the 8-field state once, plus the CFL read) per step time, as a fraction
+    of the 8 TB/s peak."""
+    nbytes = STEP_WORDS * esize * ncell
+    ach = nbytes / sec_per_step / 1e9
+    return {"bound": "hbm", "words_per_cell": STEP_WORDS, "bytes_per_step": nbytes, "achieved": round(ach, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "ms_per_step_at_60pct": round(nbytes / (0.6 * HBM_PEAK_GBS * 1e9) * 1e3, 4)}
+
+
 def roofline(kern, ncell, esize, n):
     total = {k: v[0] for k, v in kern.items() if v[1] > 0}
     dom = max(total, key=total.get)
@@ -253,9 +264,16 @@ def _pct(xs, q):
 
 def build_states(P, specs):
     """Every request's initial state, built on a few host threads before any timed run (a request
-    arrives with its state)."""
-    prod = _Producer(P, specs)
-    return [prod.next() for _ in specs]
+    arrives with its state). Vortex requests of one grid size and dtype have the same initial state,
+    so they share one (read-only) array; each blast request has its own."""
+    key = [("vortex", sp["n"], sp["dtype"]) if sp["kind"] == "vortex" else i for i, sp in enumerate(specs)]
+    uniq = {}
+    for i, k in enumerate(key):
+        uniq.setdefault(k, i)
+    order = sorted(uniq.values())
+    prod = _Producer(P, [specs[i] for i in order])
+    built = {i: prod.next() for i in order}
+    return [built[uniq[k]] for k in key]
 
 
 def serve_once(B, P, specs, arrivals, budget, max_cells=None, states=None):
@@ -319,33 +337,52 @@ def _scratch(sp):
     return _scratch_bufs[key]
 
 
-def run_serving(B, P, count, fracs, budget, steps, max_cells=None):
+def run_serving(B, P, count, fracs, budget, steps, max_cells=None, sat_count=256):
     import numpy as np
     import torch
 
     specs = P.serving_specs(count, nsteps=steps)
     work = [sp["n"] ** 3 * sp["nsteps"] for sp in specs]
+    t0 = time.perf_counter()
     states = build_states(P, specs)
-    # plain solves one at a time: the service time of each request alone, as a serial server would
-    # spend it (create, copy in, step, copy out, release), and its stepping part
-    service, stepping = [], []
-    for sp, st in zip(specs, states):
-        n = sp["n"]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        with B.Solver(n, n, n, sp["gamma"], B.MHD_BC_PERIODIC, sp["dtype"]) as sv:
-            sv.set_state(st)
-            t1 = time.perf_counter()
-            sv.step(sp["nsteps"], 0.7)
-            stepping.append(time.perf_counter() - t1)
-            sv.get_state()
-        service.append(time.perf_counter() - t0)
-    print("bench: serving, plain solves %.2f s (stepping %.2f s)" % (sum(service), sum(stepping)), file=sys.stderr,
+    print("bench: serving, %d request states built in %.1f s" % (count, time.perf_counter() - t0), file=sys.stderr,
           flush=True)
-    # saturation: every request present at the start
-    lat0, span0, _ = serve_once(B, P, specs, [0.0] * count, budget, max_cells, states)
-    sat = count / span0
-    print("bench: serving, saturation %.2f requests/s" % sat, file=sys.stderr, flush=True)
+    # plain solves one at a time, as a serial server would spend them (create, copy in, step, copy out,
+    # release), on a stream of their own so that their steps replay from graphs. A solve's time depends
+    # on its grid and dtype only (the kernels do the same work for any values), so each (n, dtype) class
+    # is timed twice on one of its requests and the faster time stands for every request of the class.
+    pstream = torch.cuda.Stream()
+    first = {}
+    for i, sp in enumerate(specs):
+        first.setdefault((sp["n"], sp["dtype"]), i)
+    svc, stp = {}, {}
+    for key, i in sorted(first.items()):
+        sp, st = specs[i], states[i]
+        n = sp["n"]
+        best = None
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            with B.Solver(n, n, n, sp["gamma"], B.MHD_BC_PERIODIC, sp["dtype"]) as sv:
+                B.mhd_set_stream(sv.h, pstream)
+                sv.set_state(st)
+                t1 = time.perf_counter()
+                sv.step(sp["nsteps"], 0.7)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                sv.get_state()
+            tt = (time.perf_counter() - t0, t2 - t1)
+            best = tt if best is None or tt[0] < best[0] else best
+        svc[key], stp[key] = best
+    service = [svc[(sp["n"], sp["dtype"])] for sp in specs]
+    stepping = [stp[(sp["n"], sp["dtype"])] for sp in specs]
+    print("bench: serving, plain solves %.2f s (stepping %.2f s) for all %d requests" % (sum(service), sum(stepping),
+          count), file=sys.stderr, flush=True)
+    # saturation: the first sat_count requests all present at the start
+    m = min(sat_count, count)
+    lat0, span0, _ = serve_once(B, P, specs[:m], [0.0] * m, budget, max_cells, states[:m])
+    sat = m / span0
+    print("bench: serving, saturation %.2f requests/s (first %d requests)" % (sat, m), file=sys.stderr, flush=True)
     rng = np.random.Generator(np.random.PCG64(P.MASTER_SEED + 501))
     gaps = rng.exponential(1.0, size=count)
     points = []
@@ -359,24 +396,29 @@ def run_serving(B, P, count, fracs, budget, steps, max_cells=None):
             fin = max(a, fin) + sv
             slat.append(fin - a)
         points.append({"rate_frac": f, "rate_rps": round(lam, 3), "p50_s": _pct(lat, 50), "p99_s": _pct(lat, 99),
-                       "cell_updates_per_s": round(sum(work) / span, 1), "late_submissions": late,
-                       "plain_fcfs_p50_s": _pct(slat, 50), "plain_fcfs_p99_s": _pct(slat, 99)})
+                       "makespan_s": round(span, 2), "cell_updates_per_s": round(sum(work) / span, 1),
+                       "late_submissions": late, "plain_fcfs_p50_s": _pct(slat, 50),
+                       "plain_fcfs_p99_s": _pct(slat, 99), "plain_fcfs_makespan_s": round(fin, 2)})
         print("bench: serving at %.2f x saturation: p50 %.3f s p99 %.3f s" % (f, points[-1]["p50_s"],
               points[-1]["p99_s"]), file=sys.stderr, flush=True)
+    del states
     return {
         "workload": "%d requests: blast / extruded Orszag-Tang, n^3 with n in {32..192}, FP32/FP64, %d steps, "
-                    "Poisson arrivals" % (count, steps),
+                    "Poisson arrivals at %s x the saturation rate" % (count, steps, ", ".join("%g" % f for f in fracs)),
         "requests": count,
         "hbm_budget_bytes": budget,
         "max_running_cells": max_cells if max_cells is not None else 1 << 24,
         "cell_updates": sum(work),
+        "saturation_requests": m,
         "saturation_rps": round(sat, 3),
-        "saturation_cell_updates_per_s": round(sum(work) / span0, 1),
+        "saturation_cell_updates_per_s": round(sum(work[:m]) / span0, 1),
         "saturation_p50_s": _pct(lat0, 50),
         "saturation_p99_s": _pct(lat0, 99),
         "plain_serial_cell_updates_per_s": round(sum(work) / sum(service), 1),
         "plain_serial_stepping_only_cell_updates_per_s": round(sum(work) / sum(stepping), 1),
-        "speedup_vs_plain_serial": round(sum(service) / span0, 3),
+        "plain_service_s_per_class": {"%d^3 %s" % (k[0], "fp64" if k[1] == 1 else "fp32"): round(v, 4)
+                                      for k, v in sorted(svc.items())},
+        "speedup_vs_plain_serial": round(sum(service[:m]) / span0, 3),
         "points": points,
     }
 
@@ -435,33 +477,70 @@ def run_paper_configs(B, P, steps=20, warmup=3, only=None):
     return out
 
 
+def host_cpus():
+    """CPUs this process may run on (the box's share, whatever nproc shows)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        avail = min(avail, int(env))
+    return max(1, avail)
+
+
 def cpu_baseline(P, n, sample):
-    """The oracle, single thread, on a bounded sample: one full step of a
-    sample^3 box cut from the centre of the n^3 blast (outflow edges)."""
+    """The oracle on the host cores: the OpenMP build on every available core
+    for 1 warm-up + 2 timed full steps of the n^3 blast itself (the value),
+    and the serial build pinned to one core for up to 3 steps of a sample^3
+    box cut from the centre of the same blast (outflow edges)."""
     import numpy as np
 
     import oracle
 
+    oracle.build()
     s = P.blast(n)
+    threads = host_cpus()
+    g = oracle.Grid(n, n, n, 5.0 / 3.0, oracle.PERIODIC)
+    used = oracle.set_threads(threads)
+    st, t, k = oracle.run(g, s, 1, 0.7)
+    t0 = time.perf_counter()
+    st, t, k = oracle.run(g, st, 2, 0.7, t, k)
+    par = time.perf_counter() - t0
+    oracle.set_threads(1)
+    del st
     lo = (n - sample) // 2
     box = np.ascontiguousarray(s[:, lo:lo + sample, lo:lo + sample, lo:lo + sample])
-    g = oracle.Grid(sample, sample, sample, 5.0 / 3.0, oracle.OUTFLOW)
-    oracle.build()
+    del s
+    gb = oracle.Grid(sample, sample, sample, 5.0 / 3.0, oracle.OUTFLOW)
+    try:
+        old_aff = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {min(old_aff)})
+    except (AttributeError, OSError):
+        old_aff = None
     t0 = time.perf_counter()
     steps = 0
     while True:
-        box, _, _ = oracle.run(g, box, 1, 0.7, 0.0, steps)
+        box, _, _ = oracle.run(gb, box, 1, 0.7, 0.0, steps)
         steps += 1
         if time.perf_counter() - t0 > 8.0 or steps >= 3:
             break
-    dt = time.perf_counter() - t0
+    ser = time.perf_counter() - t0
+    if old_aff is not None:
+        os.sched_setaffinity(0, old_aff)
     return {
-        "value": round(sample ** 3 * steps / dt, 1),
+        "value": round(n ** 3 * 2 / par, 1),
         "unit": "cell-updates/s",
-        "cores": 1,
+        "cores": used,
         "kind": "oracle",
-        "sample": "%d full step(s) of a %d^3 box cut from the centre of the %d^3 blast, serial FP64 C oracle, "
-                  "host CPU: %s" % (steps, sample, n, cpu_model()),
+        "sample": "1 warm-up + 2 timed full steps of the %d^3 blast (periodic), FP64 C oracle built with OpenMP "
+                  "(-O3, no FMA contraction; pencils of each sweep shared among %d threads, bitwise the serial "
+                  "build)" % (n, used),
+        "seconds_per_step": round(par / 2, 3),
+        "serial": {"value": round(sample ** 3 * steps / ser, 1), "cores": 1,
+                   "sample": "%d full step(s) of a %d^3 box cut from the centre of the %d^3 blast (outflow edges), "
+                             "serial build pinned to one core" % (steps, sample, n)},
+        "host": {"cpu_model": cpu_model(), "nproc": os.cpu_count(), "available_cpus": threads},
     }
 
 
@@ -483,8 +562,10 @@ def main():
     ap.add_argument("--paper-only", type=int, default=None, choices=range(len(PAPER_CONFIGS)),
                     help="run only this one of the paper's timing workloads (0 Brio-Wu 4096, 1 Orszag-Tang 512^2, "
                          "2 Orszag-Tang 1024^2, 3 blast 128^3), with per-kernel times, and print its JSON line")
-    ap.add_argument("--serve-count", type=int, default=96)
-    ap.add_argument("--serve-rates", default="0.5,1.0", help="arrival rates as fractions of saturation")
+    ap.add_argument("--serve-count", type=int, default=1024)
+    ap.add_argument("--serve-rates", default="0.75,1.0,1.25", help="arrival rates as fractions of saturation")
+    ap.add_argument("--serve-sat-count", type=int, default=256,
+                    help="requests of the closed-loop run that measures the saturation rate")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--serve-steps", type=int, default=100)
     ap.add_argument("--serve-max-cells", type=int, default=None,
@@ -543,6 +624,7 @@ def main():
                    "global_batch": 1, "parallelism": "single GPU"},
         "roofline": roof,
         "effective_step_bandwidth_GBs": round(STEP_WORDS * 8 * ncell * args.steps / sec64 / 1e9, 1),
+        "step_roofline": step_roofline(sec64 / args.steps, ncell, 8),
         "step_words": {"minimum": STEP_WORDS, "this_design": DESIGN_STEP_WORDS, "cfl_fused_into_last_sweep": True},
         "kernels_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in kern64.items()},
         "instrumented_ms_per_step": round(inst64 * 1e3 / args.steps, 4),
@@ -557,6 +639,7 @@ def main():
             "ms_per_step": round(sec32 * 1e3 / args.steps, 4),
             "roofline": roof32,
             "effective_step_bandwidth_GBs": round(STEP_WORDS * 4 * ncell * args.steps / sec32 / 1e9, 1),
+            "step_roofline": step_roofline(sec32 / args.steps, ncell, 4),
             "kernels_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in kern32.items()},
             "instrumented_ms_per_step": round(inst32 * 1e3 / args.steps, 4),
         }
@@ -569,7 +652,8 @@ def main():
     if not args.no_serve:
         print("bench: serving workload", file=sys.stderr, flush=True)
         out["serving"] = run_serving(B, P, args.serve_count, [float(x) for x in args.serve_rates.split(",")],
-                                     int(args.serve_budget_gb * (1 << 30)), args.serve_steps, args.serve_max_cells)
+                                     int(args.serve_budget_gb * (1 << 30)), args.serve_steps, args.serve_max_cells,
+                                     args.serve_sat_count)
     if rank == 0 and not args.no_cpu_baseline:
         print("bench: cpu oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(P, n, args.cpu_sample)
