@@ -225,6 +225,36 @@ def test_fp32_smooth_problems(B, orc):
         assert H.rel_l1(got[f], want[f]) <= F32_SMOOTH_TOL, f
 
 
+def test_fp32_smooth_gate_3d_and_orszag_tang_512(B, orc):
+    """The FP32 gate (relative L1 <= 1e-5 per field after 10 steps against the
+    FP64 oracle) on a 3D problem and on the 512^2 Orszag-Tang configuration:
+    an oblique Alfven wave of amplitude 0.1 along k = (1, 1, 1) on 48^3 (every
+    field, including the three field components), and Orszag-Tang 512^2 with
+    all eight fields."""
+    make, _ = H.wave_setup("alfven", 48, 48, 48, (1, 1, 1), 0.1, b0dir=(1.0, 0.6, 0.3))
+    s = make(0.0)
+    g = orc.Grid(48, 48, 48, H.GAMMA53)
+    note("alfven 48^3 k=(1,1,1) fp32")
+    got, _ = gpu_run(B, s, H.GAMMA53, 0, B.MHD_F32, 10)
+    orc.set_threads(4)
+    try:
+        want, _, _ = orc.run(g, s, 10, 0.7)
+        errs = [H.rel_l1(got[f], want[f]) for f in range(8)]
+        note("alfven 48^3 fp32 rel L1 per field: " + " ".join("%.1e" % e for e in errs))
+        assert max(errs) <= F32_SMOOTH_TOL, errs
+        n = 512
+        s = P.orszag_tang(n)
+        g = orc.Grid(n, n, 1, H.GAMMA53)
+        note("orszag-tang 512^2 fp32, 10 steps")
+        got, _ = gpu_run(B, s, H.GAMMA53, 0, B.MHD_F32, 10)
+        want, _, _ = orc.run(g, s, 10, 0.7)
+    finally:
+        orc.set_threads(1)
+    errs = [H.rel_l1(got[f], want[f]) for f in range(8) if np.abs(want[f]).sum() > 0]
+    note("orszag-tang 512^2 fp32 rel L1 per field: " + " ".join("%.1e" % e for e in errs))
+    assert max(errs) <= F32_SMOOTH_TOL, errs
+
+
 # --------------------------------------------------------------- invariants on the GPU
 
 def test_gpu_uniform_state_bitwise(B):

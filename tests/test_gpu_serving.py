@@ -45,11 +45,21 @@ def small_requests():
     out = []
     for k, sp in enumerate(specs):
         npd = np.float64 if sp["dtype"] == 1 else np.float32
-        out.append((P.serving_state(sp, npd), sp["gamma"], k % 2, sp["dtype"], 4 + (k * 3) % 9))
+        out.append((P.serving_state(sp, npd), sp["gamma"], k % 2, sp["dtype"], 4 + (k * 3) % 9, sp["kind"]))
     return out
 
 
-def test_served_results_equal_alone_under_a_tight_budget(B):
+def rel_linf(a, b):
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / (den if den > 0 else 1.0))
+
+
+def rel_l1(a, b):
+    den = np.abs(b).sum()
+    return float(np.abs(a - b).sum() / (den if den > 0 else 1.0))
+
+
+def test_served_results_equal_alone_under_a_tight_budget(B, orc):
     reqs = small_requests()
     sizes = sorted(B.mhd_batch_problem_bytes(*r[0].shape[:0:-1], r[3]) for r in reqs)
     budget = sum(sizes[-3:])          # at most about three requests resident at once
@@ -65,7 +75,7 @@ def test_served_results_equal_alone_under_a_tight_budget(B):
             if k < len(reqs) and ticks % 3 == 0:
                 for _ in range(2):
                     if k < len(reqs):
-                        st, gm, bc, dt, ns = reqs[k]
+                        st, gm, bc, dt, ns, _ = reqs[k]
                         ids[srv.submit(st, gm, bc, dt, ns)] = k
                         k += 1
             srv.tick()
@@ -82,12 +92,34 @@ def test_served_results_equal_alone_under_a_tight_budget(B):
     # first come, first served: admission follows submission order
     adm = [i for _, i in sorted(order)]
     assert adm == sorted(adm)
-    for i, (st, gm, bc, dt, ns) in enumerate(reqs):
+    for i, (st, gm, bc, dt, ns, kind) in enumerate(reqs):
         got, info = results[i]
         want, (t, s) = alone(B, st, gm, bc, dt, ns)
         assert info["steps"] == ns == s
         assert info["t_sim"] == t
         assert np.array_equal(got, want), i
+    # and against the oracle on the same (rounded) initial state: FP64 within
+    # 1e-10 relative L-infinity per field; FP32 within 1e-5 relative L1 per
+    # field on the smooth vortex; the blast waves are shock problems, whose
+    # FP32 error is reported and held to 1e-3
+    for i, (st, gm, bc, dt, ns, kind) in enumerate(reqs):
+        got, info = results[i]
+        nz, ny, nx = st.shape[1:]
+        want, tw, sw = orc.run(orc.Grid(nx, ny, nz, gm, bc), st.astype(np.float64), ns, 0.7)
+        assert sw == ns
+        got = got.astype(np.float64)
+        if dt == B.MHD_F64:
+            errs = [rel_linf(got[f], want[f]) for f in range(8)]
+            note("request %d (%s %d^3, fp64, bc %d, %d steps): max rel Linf vs oracle %.1e" % (i, kind, nx, bc, ns,
+                                                                                             max(errs)))
+            assert max(errs) <= 1e-10, (i, errs)
+            assert info["t_sim"] == tw
+        else:
+            errs = [rel_l1(got[f], want[f]) for f in range(8) if np.abs(want[f]).sum() > 0]
+            note("request %d (%s %d^3, fp32, bc %d, %d steps): max rel L1 vs oracle %.1e" % (i, kind, nx, bc, ns,
+                                                                                           max(errs)))
+            assert max(errs) <= (1e-5 if kind == "vortex" else 1e-3), (i, errs)
+            assert abs(info["t_sim"] - tw) <= 1e-5 * tw
 
 
 def test_oversized_request_is_rejected(B):
@@ -134,7 +166,7 @@ def test_cell_cap_admits_one_request_at_a_time(B):
         with pytest.raises(B.MHDError) as ei:
             B.mhd_server_set_max_cells(srv.s, -1)
         assert ei.value.code == B.MHD_ERR_ARG
-        ids = {srv.submit(st, gm, bc, dt, ns): k for k, (st, gm, bc, dt, ns) in enumerate(reqs)}
+        ids = {srv.submit(st, gm, bc, dt, ns): k for k, (st, gm, bc, dt, ns, _) in enumerate(reqs)}
         results = {}
         ticks = 0
         while len(results) < len(reqs):
@@ -151,7 +183,7 @@ def test_cell_cap_admits_one_request_at_a_time(B):
             for rid in srv.finished():
                 results[ids[rid]] = srv.take(rid)
             assert ticks < 1000
-    for k, (st, gm, bc, dt, ns) in enumerate(reqs):
+    for k, (st, gm, bc, dt, ns, _) in enumerate(reqs):
         assert np.array_equal(results[k], alone(B, st, gm, bc, dt, ns)[0]), k
 
 
@@ -165,7 +197,7 @@ def test_lent_states_give_the_same_results(B):
     note("serving lent states")
     with B.Server(1 << 30) as srv:
         ids = {}
-        for k, (st, gm, bc, dt, ns) in enumerate(reqs):
+        for k, (st, gm, bc, dt, ns, _) in enumerate(reqs):
             ids[srv.submit(np.ascontiguousarray(st), gm, bc, dt, ns, lend=True)] = k
         rb = srv.submit(bad, 5.0 / 3.0, 0, B.MHD_F64, 3, lend=True)
         results, failed = {}, None
@@ -182,5 +214,5 @@ def test_lent_states_give_the_same_results(B):
                 break
     assert failed is not None and failed[0]["status"] == B.MHD_ERR_ARG
     assert np.array_equal(failed[1], bad)
-    for k, (st, gm, bc, dt, ns) in enumerate(reqs):
+    for k, (st, gm, bc, dt, ns, _) in enumerate(reqs):
         assert np.array_equal(results[k], alone(B, st, gm, bc, dt, ns)[0]), k
