@@ -125,6 +125,23 @@ int mhd_step(mhd_t* h, int n, double cfl);
  * nothing). Synchronises the stream. */
 int mhd_divb_max(mhd_t* h, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * quantity of mhd_divb_max for a state in the caller's device memory, with no
+ * handle. dev_state: 8 * nx * ny * nz elements of dtype in the state layout
+ * above (only the face fields are read); bc, dtype and the sizes as in
+ * mhd_create. The maximum is written, as a double, to the caller's device
+ * pointer dev_out, asynchronously on stream (hipStream_t as void*, null = the
+ * null stream); nothing is allocated and nothing synchronises. The reduction
+ * uses a fixed device array of the library (8192 slots and a control block,
+ * about 64 KiB, one copy per device, held until the process ends); every
+ * grid that mhd_create accepts fits it. All calls on one device share that
+ * array, so calls whose work overlaps on a device (other streams, other host
+ * threads) race: order them. Errors: MHD_ERR_ARG for null pointers, sizes,
+ * bc or dtype out of range; MHD_ERR_DEVICE if a launch fails. */
+int mhd_divb_max_noalloc(const void* dev_state, int nx, int ny, int nz, int bc, int dtype, double* dev_out,
+                         void* stream);
+
 /* Simulation time and step counter (s mod 3 selects the sweep order). */
 int mhd_get_time(mhd_t* h, double* t, int64_t* s);
 int mhd_set_time(mhd_t* h, double t, int64_t s);

@@ -51,6 +51,7 @@ def lib():
             "mhd_get_state_device": ([vp, vp], i),
             "mhd_step": ([vp, i, d], i),
             "mhd_divb_max": ([vp, ctypes.POINTER(d)], i),
+            "mhd_divb_max_noalloc": ([vp, i, i, i, i, i, vp, vp], i),
             "mhd_get_time": ([vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int64)], i),
             "mhd_set_time": ([vp, d, ctypes.c_int64], i),
             "mhd_set_stop_time": ([vp, d], i),
@@ -174,6 +175,13 @@ def mhd_divb_max(h) -> float:
     v = ctypes.c_double()
     _check(lib().mhd_divb_max(h, ctypes.byref(v)))
     return v.value
+
+
+def mhd_divb_max_noalloc(dev_state, nx: int, ny: int, nz: int, bc: int, dtype: int, dev_out, stream=None):
+    """dev_state / dev_out: device tensors (or raw device addresses); dev_out
+    receives one double, asynchronously on `stream`."""
+    sp = None if stream is None else (stream if isinstance(stream, int) else int(stream.cuda_stream))
+    _check(lib().mhd_divb_max_noalloc(_dev_ptr(dev_state), nx, ny, nz, bc, dtype, _dev_ptr(dev_out), sp))
 
 
 def mhd_get_time(h):

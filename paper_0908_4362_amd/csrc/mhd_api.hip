@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -304,6 +305,33 @@ namespace mhd {
 int report(int code, const char* msg) { return fail(code, msg); }
 int report_hip(hipError_t e, const char* where) { return hip_fail(e, where); }
 }  // namespace mhd
+
+// ---- div B without allocation: the reduction slots and the control block
+// the finisher writes live in a fixed device array (one copy per device,
+// kept until the process ends), whose address is looked up once per device.
+namespace {
+constexpr int kNoAllocSlots = 8192;   // reduce_slots never exceeds it
+constexpr size_t kNoAllocBytes = kNoAllocSlots * sizeof(unsigned long long) + 256;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (the host-side name of the
+// array is a stand-in that no kernel may be given).
+int scratch_ptr(int dev, void** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(MHD_ERR_ARG, "device index beyond the supported count");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MHD_OK;
+}
+}  // namespace
 
 extern "C" {
 
@@ -619,6 +647,40 @@ int mhd_divb_max(mhd_t* h, double* out)
     Ctl c;
     if (int rc = read_ctl(h, &c)) return rc;
     *out = c.divb;
+    return MHD_OK;
+}
+
+int mhd_divb_max_noalloc(const void* dev_state, int nx, int ny, int nz, int bc, int dtype, double* dev_out,
+                         void* stream)
+{
+    g_err.clear();
+    if (!dev_state || !dev_out) return fail(MHD_ERR_ARG, "null state or output pointer");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(MHD_ERR_ARG, "grid sizes must be >= 1");
+    if ((long long)nx * ny * nz > (1LL << 36)) return fail(MHD_ERR_ARG, "grid too large (more than 2^36 cells)");
+    if (bc != MHD_BC_PERIODIC && bc != MHD_BC_OUTFLOW) return fail(MHD_ERR_ARG, "unknown boundary condition");
+    if (dtype != MHD_F32 && dtype != MHD_F64) return fail(MHD_ERR_ARG, "unknown dtype");
+    Grid g;
+    g.n[0] = nx;
+    g.n[1] = ny;
+    g.n[2] = nz;
+    g.bc = bc;
+    g.N = (long long)nx * ny * nz;
+    if (mhd::reduce_slots(g) > kNoAllocSlots) return fail(MHD_ERR_ARG, "reduction needs more slots than the scratch");
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev), "hipGetDevice");
+    void* base = nullptr;
+    if (int rc = scratch_ptr(dev, &base)) return rc;
+    unsigned long long* parts = static_cast<unsigned long long*>(base);
+    Ctl* ctl = reinterpret_cast<Ctl*>(static_cast<char*>(base) + kNoAllocSlots * sizeof(unsigned long long));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t es = dtype == MHD_F64 ? 8 : 4;
+    const void* bfield = static_cast<const char*>(dev_state) + 5 * (size_t)g.N * es;
+    int np = 0;
+    hipError_t e = dtype == MHD_F64 ? mhd::launch_divb<double>(static_cast<const double*>(bfield), g, parts, &np, s)
+                                    : mhd::launch_divb<float>(static_cast<const float*>(bfield), g, parts, &np, s);
+    if (e != hipSuccess) return hip_fail(e, "div B launch");
+    HIPCHK(mhd::launch_finish(parts, np, 1, 0.0, ctl, s), "div B finish launch");
+    HIPCHK(hipMemcpyAsync(dev_out, &ctl->divb, sizeof(double), hipMemcpyDeviceToDevice, s), "div B result copy");
     return MHD_OK;
 }
 

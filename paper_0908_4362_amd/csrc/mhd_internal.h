@@ -40,6 +40,7 @@ int report_hip(hipError_t e, const char* where);
 // graph reduces exactly the slots the previous producer wrote, whichever
 // launch that was (a fluid sweep of any axis, or the standalone pass).
 size_t reduce_capacity(const Grid& g);   // largest number of parts any launch writes
+int reduce_slots(const Grid& g);         // parts launch_cfl and launch_divb write (at most 8192)
 // what 0: c_max over ctl->nparts slots (and the dt rule if cfl > 0);
 // what 1: max |div B| over nparts slots into ctl->divb
 hipError_t launch_finish(const unsigned long long* parts, int nparts, int what, double cfl, Ctl* ctl,

@@ -68,6 +68,8 @@ hipError_t launch_finish(const unsigned long long* parts, int nparts, int what, 
     return hipGetLastError();
 }
 
+int reduce_slots(const Grid& g) { return reduce_blocks(g); }
+
 size_t reduce_capacity(const Grid& g)
 {
     size_t cap = (size_t)reduce_blocks(g);
