@@ -86,6 +86,12 @@ int mhd_set_stream(mhd_t* h, void* stream);
  * host cost that dominates small grids. Results are identical either way. */
 int mhd_set_graphs(mhd_t* h, int enable);
 
+/* Run each reverse L_d of a periodic grid (field update, then fluid update,
+ * Sec. 4.3) as one launch that keeps the new field in registers (enable = 1,
+ * the default), or as two launches (0). Results are identical either way;
+ * grids with outflow boundaries always take two launches. */
+int mhd_set_fusion(mhd_t* h, int enable);
+
 /* Copy a state in (layout above) from host memory or from device memory
  * (step 3 of the program flow of Sec. 4.2: the initial u and face B to
  * device memory; with t set to 0 as in step 2);
@@ -183,7 +189,10 @@ enum {
     MHD_K_CT_X = 4,      /* field update along d: MHD_K_CT_X + d             */
     MHD_K_CT_Y = 5,
     MHD_K_CT_Z = 6,
-    MHD_K_COUNT = 7
+    MHD_K_CTFLUID_X = 7, /* reverse L_d fused into one launch (field update  */
+    MHD_K_CTFLUID_Y = 8, /* then fluid update): MHD_K_CTFLUID_X + d           */
+    MHD_K_CTFLUID_Z = 9,
+    MHD_K_COUNT = 10
 };
 
 /* Start (enable = 1, clears the totals) or stop (0) recording. */

@@ -19,8 +19,9 @@ LIB_PATH = os.path.join(HERE, "libmhd.so")
 MHD_OK, MHD_ERR_ARG, MHD_ERR_OOM, MHD_ERR_DEVICE, MHD_ERR_NONFINITE = 0, -1, -2, -3, -4
 MHD_BC_PERIODIC, MHD_BC_OUTFLOW = 0, 1
 MHD_F32, MHD_F64 = 0, 1
-MHD_K_CFL, MHD_K_FLUID_X, MHD_K_FLUID_Y, MHD_K_FLUID_Z, MHD_K_CT_X, MHD_K_CT_Y, MHD_K_CT_Z, MHD_K_COUNT = range(8)
-KERNEL_KINDS = ("cfl", "fluid_x", "fluid_y", "fluid_z", "ct_x", "ct_y", "ct_z")
+(MHD_K_CFL, MHD_K_FLUID_X, MHD_K_FLUID_Y, MHD_K_FLUID_Z, MHD_K_CT_X, MHD_K_CT_Y, MHD_K_CT_Z, MHD_K_CTFLUID_X,
+ MHD_K_CTFLUID_Y, MHD_K_CTFLUID_Z, MHD_K_COUNT) = range(11)
+KERNEL_KINDS = ("cfl", "fluid_x", "fluid_y", "fluid_z", "ct_x", "ct_y", "ct_z", "ctfluid_x", "ctfluid_y", "ctfluid_z")
 MHD_D_PRESSURE, MHD_D_MAGNETIC_PRESSURE, MHD_D_SPEED, MHD_D_DIVB, MHD_D_CFL_SPEED, MHD_D_COUNT = range(6)
 
 _lib = None
@@ -45,6 +46,7 @@ def lib():
             "mhd_destroy": ([vp], i),
             "mhd_set_stream": ([vp, vp], i),
             "mhd_set_graphs": ([vp, i], i),
+            "mhd_set_fusion": ([vp, i], i),
             "mhd_set_state": ([vp, vp], i),
             "mhd_set_state_device": ([vp, vp], i),
             "mhd_get_state": ([vp, vp], i),
@@ -145,6 +147,10 @@ def mhd_set_stream(h, stream):
 
 def mhd_set_graphs(h, enable: bool):
     _check(lib().mhd_set_graphs(h, 1 if enable else 0))
+
+
+def mhd_set_fusion(h, enable: bool):
+    _check(lib().mhd_set_fusion(h, 1 if enable else 0))
 
 
 def mhd_set_state(h, host_state: np.ndarray):

@@ -41,6 +41,7 @@ struct mhd_solver {
     bool bound;           // buffers live in a caller-owned workspace (mhd_bind_workspace)
     // full steps replayed from HIP graphs, one per sweep order (s mod 3)
     bool graphs;
+    bool fusion;          // reverse L_d as one fused launch where it applies
     hipGraphExec_t exec[3];
     double exec_cfl[3];
     // optional per-kernel timing with HIP events on the handle's stream
@@ -154,6 +155,34 @@ int ct(mhd_solver* h, int axis, double dt)
     return MHD_OK;
 }
 
+// Reverse L_d in one launch: the field update along axis, then the fluid
+// update on the new field (both copies flip).
+template <typename T>
+int ct_fluid(mhd_solver* h, int axis, double dt, bool with_cfl)
+{
+    const T* uin = static_cast<const T*>(h->u[h->ucur]);
+    T* uout = static_cast<T*>(h->u[h->ucur ^ 1]);
+    const T* bin = static_cast<const T*>(h->b[h->bcur]);
+    T* bout = static_cast<T*>(h->b[h->bcur ^ 1]);
+    int rc = timed(h, MHD_K_CTFLUID_X + axis,
+                   [&] {
+                       return mhd::launch_ct_fluid<T>(axis, uin, uout, bin, bout, h->g, h->gamma, h->ctl, dt,
+                                                      with_cfl ? h->parts : nullptr, h->stream);
+                   },
+                   "fused field and fluid sweep launch");
+    if (rc) return rc;
+    h->ucur ^= 1;
+    h->bcur ^= 1;
+    return MHD_OK;
+}
+
+// The fused launch covers reverse L_d of a periodic grid whose fluid sweep
+// along d runs (more than one cell).
+bool fused_reverse(const mhd_solver* h, int axis)
+{
+    return h->fusion && h->g.bc == MHD_BC_PERIODIC && h->g.n[axis] > 1;
+}
+
 // The 12 sub-operations of one full step with sweep-order index s
 // (eq. L_sequence): forward L_d = fluid_d then the field update along d;
 // reverse L_d with the field update first; axis order (x,y,z), (z,x,y),
@@ -186,6 +215,10 @@ int sweeps(mhd_solver* h, long long s, double dt, bool reduce_cmax)
         if ((rc = ct<T>(h, p[a], dt))) return rc;
     }
     for (int a = 2; a >= 0; a--) {
+        if (fused_reverse(h, p[a])) {
+            if ((rc = ct_fluid<T>(h, p[a], dt, reduce_cmax && a == 0))) return rc;
+            continue;
+        }
         if ((rc = ct<T>(h, p[a], dt))) return rc;
         if (h->g.n[p[a]] > 1)
             if ((rc = fluid<T>(h, p[a], dt, reduce_cmax && a == 0))) return rc;
@@ -395,6 +428,7 @@ int mhd_create(int nx, int ny, int nz, double gamma, int bc, int dtype, mhd_t** 
     h->cmax_valid = false;
     h->bound = false;
     h->graphs = true;
+    h->fusion = true;
     for (int q = 0; q < 3; q++) {
         h->exec[q] = nullptr;
         h->exec_cfl[q] = 0.0;
@@ -512,6 +546,16 @@ int mhd_set_graphs(mhd_t* h, int enable)
     HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
     if (!enable) drop_graphs(h);
     h->graphs = enable != 0;
+    return MHD_OK;
+}
+
+int mhd_set_fusion(mhd_t* h, int enable)
+{
+    if (int rc = check(h)) return rc;
+    if (int rc = set_current(h)) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
+    drop_graphs(h);   // captured with the other launch sequence
+    h->fusion = enable != 0;
     return MHD_OK;
 }
 

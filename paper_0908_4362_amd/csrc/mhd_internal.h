@@ -65,6 +65,13 @@ hipError_t launch_fluid(int axis, const T* u_in, T* u_out, const T* b, Grid g, d
 template <typename T>
 hipError_t launch_ct(int axis, const T* u, const T* b_in, T* b_out, Grid g, const Ctl* ctl, double dt,
                      hipStream_t s);
+// Reverse L_d along any axis of a periodic grid in one launch: the field
+// update (reads u, b_in; writes b_out) then the fluid update on the new field
+// (reads u_in; writes u_out), the same results as launch_ct then
+// launch_fluid. With parts non-null the fluid part stores the c_max slots.
+template <typename T>
+hipError_t launch_ct_fluid(int axis, const T* u_in, T* u_out, const T* b_in, T* b_out, Grid g, double gamma,
+                           Ctl* ctl, double dt, unsigned long long* parts, hipStream_t s);
 // The field sweep along axis 1 or 2 when that axis has one cell: the fixed
 // point of the marching pipeline, evaluated per cell (same results bit for
 // bit, one pass over the fields instead of a warm-up per chunk).

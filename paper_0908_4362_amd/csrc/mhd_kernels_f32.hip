@@ -16,6 +16,8 @@ template hipError_t launch_ct<float>(int, const float*, const float*, float*, Gr
                                      hipStream_t);
 template hipError_t launch_ct_flat<float>(int, const float*, const float*, float*, Grid, const Ctl*, double,
                                            hipStream_t);
+template hipError_t launch_ct_fluid<float>(int, const float*, float*, const float*, float*, Grid, double, Ctl*, double,
+                                           unsigned long long*, hipStream_t);
 template void tile_default<float>(const Grid&, int, int*, int*);
 template void tile_candidates<float>(const Grid&, int, std::vector<std::pair<int, int>>&);
 template unsigned tile_blocks<float>(const Grid&, int, int, int);

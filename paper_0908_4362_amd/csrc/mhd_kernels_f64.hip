@@ -74,8 +74,12 @@ size_t reduce_capacity(const Grid& g)
 {
     size_t cap = (size_t)reduce_blocks(g);
     cap = std::max(cap, (size_t)x_wave_blocks(g));
-    for (int axis = 1; axis <= 2; axis++)
+    cap = std::max(cap, (size_t)ct_fluid_x_blocks(g));
+    for (int axis = 1; axis <= 2; axis++) {
         cap = std::max(cap, (size_t)march_blocks(g, axis, march_chunk(g, axis, GF, kFluidMarchWaves, true), true));
+        for (int c : {fused_chunk<double>(g, axis), fused_chunk<float>(g, axis)})
+            for (bool xw : {true, false}) cap = std::max(cap, (size_t)march_blocks(g, axis, c, xw));
+    }
     return cap;
 }
 
@@ -88,6 +92,8 @@ template hipError_t launch_ct<double>(int, const double*, const double*, double*
                                       hipStream_t);
 template hipError_t launch_ct_flat<double>(int, const double*, const double*, double*, Grid, const Ctl*, double,
                                            hipStream_t);
+template hipError_t launch_ct_fluid<double>(int, const double*, double*, const double*, double*, Grid, double, Ctl*, double,
+                                           unsigned long long*, hipStream_t);
 template void tile_default<double>(const Grid&, int, int*, int*);
 template void tile_candidates<double>(const Grid&, int, std::vector<std::pair<int, int>>&);
 template unsigned tile_blocks<double>(const Grid&, int, int, int);

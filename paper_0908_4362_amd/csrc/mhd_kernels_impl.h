@@ -700,6 +700,204 @@ __global__ void __launch_bounds__(64 * MW) ct_march(const T* __restrict__ uf, co
 }
 
 
+// ---------------------------------------------------------------------------
+// Reverse L_d for d = y or z (Sec. 4.3: the field update first, then the
+// fluid update) in one march, on periodic grids: B_{e->d}, B_{f->d} (Alg. 2)
+// followed by fluid_d (Alg. 1) on the field it produced. The four EMF
+// pipelines of ct_march run ahead; they yield the new face fields of the
+// thread's own cell and of the faces its +TA / +x neighbours own (the faces
+// that enter the centred field), and the fluid pipeline of fluid_march
+// follows five cells behind, taking rho and m_d from a delay line of the
+// values the EMF pipelines loaded. Every value is computed by the same
+// expressions as in ct_march and fluid_march, so the result is the one of the
+// two launches, bit for bit, with 16 words of traffic per cell instead of
+// 8 + 13. Periodic wrapping makes the new field at a ghost position equal to
+// the new field of the cell it maps to; with outflow clamping it would not
+// (the two launches run there).
+constexpr int GCF = GF + GB;   // ghost depth of the fused march (3 + 4)
+
+template <typename T>
+struct FusedLoad {
+    T bd;              // B_d (old) of the field update's output cell h - 4
+    T me, mf, en;      // m_e, m_f, E of the fluid head cell h - 5
+};
+
+template <typename T, int D, bool CFL>
+__device__ __forceinline__ void ct_fluid_march_body(const T* __restrict__ uin, T* __restrict__ uout,
+                                                    const T* __restrict__ bin, T* __restrict__ bout, const Grid& g,
+                                                    T gamma, const Ctl* __restrict__ ctl, double dt_arg, int chunk,
+                                                    unsigned lb, unsigned long long* __restrict__ part)
+{
+    constexpr int E = (D + 1) % 3, F = (D + 2) % 3;
+    constexpr int TA = (D == 1) ? 2 : 1;
+    constexpr bool T_IS_E = (E == TA);
+    const MarchTile mt = march_tile<D, kMarchXWide<T, true>>(g, chunk, lb);
+    const int nx = g.n[0], nd = g.n[D], nt = g.n[TA];
+    const int o0 = mt.o0, o1 = mt.o1;
+    const int i = wrap_idx(mt.i, nx, g.bc), tc = wrap_idx(mt.tc, nt, g.bc);
+    const bool active = mt.active;
+    const long long N = g.N;
+    const long long sd = (D == 1) ? (long long)nx : (long long)nx * g.n[1];
+    const long long st = (TA == 1) ? (long long)nx : (long long)nx * g.n[1];
+    const long long base = i + tc * st;
+    const long long xp = wrap_idx(i + 1, nx, g.bc) - i;
+    const long long xm_ = wrap_idx(i - 1, nx, g.bc) - i;
+    const long long lo = (long long)(wrap_idx(mt.tc - 1, nt, g.bc) - tc) * st;
+    const long long hi = (long long)(wrap_idx(mt.tc + 1, nt, g.bc) - tc) * st;
+    const T* rho = uin;
+    const T* md = uin + (1 + D) * N;
+    const T* mE = uin + (1 + E) * N;
+    const T* mF = uin + (1 + F) * N;
+    const T* en = uin + 4 * N;
+    const T* BD = bin + D * N;
+    const T* BT = bin + (T_IS_E ? E : F) * N;
+    const T* BX = bin + (T_IS_E ? F : E) * N;
+    const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
+    const bool frozen = ctl->status != 0;
+    unsigned long long best = 0ull;
+
+    auto load = [&](int h, CtLoad<T>& L, FusedLoad<T>& X) {
+        const long long c = base + (long long)wrap_idx(h, nd, g.bc) * sd;
+        L.r0 = rho[c];
+        L.m0 = md[c];
+        L.bt = BT[c];
+        L.rTm = rho[c + lo];
+        L.mTm = md[c + lo];
+        L.rTp = rho[c + hi];
+        L.mTp = md[c + hi];
+        L.bt1 = BT[c + hi];
+        L.rXm = rho[c + xm_];
+        L.mXm = md[c + xm_];
+        L.rXp = rho[c + xp];
+        L.mXp = md[c + xp];
+        L.bx0 = BX[c];
+        L.bx1 = BX[c + xp];
+        X.bd = BD[base + (long long)wrap_idx(h - GB, nd, g.bc) * sd];
+        const long long cp = base + (long long)wrap_idx(h - GB - 1, nd, g.bc) * sd;
+        X.me = mE[cp];
+        X.mf = mF[cp];
+        X.en = en[cp];
+    };
+
+    EmfPipe<T> t0, t1, x0, x1;   // TA-face pencils (own, +TA), x-face pencils (own, +x)
+    t0.clear();
+    t1.clear();
+    x0.clear();
+    x1.clear();
+    FluidPipe<T> P;
+    P.clear();
+    // rho and m_d of cells h-1 .. h-5 (the fluid head is h - 5)
+    T rh[GB + 1], mh[GB + 1];
+#pragma unroll
+    for (int k = 0; k <= GB; k++) rh[k] = mh[k] = T(0);
+    // new face fields of cell h - 5 (from the previous trip)
+    T pD = T(0), pT0 = T(0), pT1 = T(0), pX0 = T(0), pX1 = T(0);
+    CtLoad<T> cur;
+    FusedLoad<T> curx;
+    load(o0 - GCF, cur, curx);
+    // unrolled 6 times, so that the shifts of the pipelines' register windows
+    // become renames (FP64 0.66 -> 0.58 ms per launch at 256^3 against the
+    // rolled loop; FP32 0.30 -> 0.26 ms)
+#pragma unroll 6
+    for (int h = o0 - GCF; h <= o1 + GCF; ++h) {
+        CtLoad<T> nxt;
+        FusedLoad<T> nxtx;
+        load(h + 1, nxt, nxtx);
+        // ---- field update (as in ct_march): EMFs at edge (h-4) + 1/2, new faces of cell q = h - 4
+        const T r0 = cur.r0, m0 = cur.m0;
+        const T rTm = cur.rTm, mTm = cur.mTm, rTp = cur.rTp, mTp = cur.mTp, bt1 = cur.bt1;
+        const T bto = t0.B4, bxo = x0.B4, bt1o = t1.B4, bx1o = x1.B4;
+        const T Gt0 = t0.push(qdiv(mTm + m0, rTm + r0), cur.bt, dt);
+        const T Gt1 = t1.push(qdiv(m0 + mTp, r0 + rTp), bt1, dt);
+        const T Gx0 = x0.push(qdiv(cur.mXm + m0, cur.rXm + r0), cur.bx0, dt);
+        const T Gx1 = x1.push(qdiv(m0 + cur.mXp, r0 + cur.rXp), cur.bx1, dt);
+        const T Ge0p = T_IS_E ? t0.G5 : x0.G5, Ge1p = T_IS_E ? t1.G5 : x1.G5;
+        const T Gf0p = T_IS_E ? x0.G5 : t0.G5, Gf1p = T_IS_E ? x1.G5 : t1.G5;
+        T nT0, nT1, nX0, nX1, nD;
+        if (frozen) {
+            nT0 = bto;
+            nT1 = bt1o;
+            nX0 = bxo;
+            nX1 = bx1o;
+            nD = curx.bd;
+        } else {
+            nT0 = bto - dt * (Gt0 - t0.G5);
+            nT1 = bt1o - dt * (Gt1 - t1.G5);
+            nX0 = bxo - dt * (Gx0 - x0.G5);
+            nX1 = bx1o - dt * (Gx1 - x1.G5);
+            nD = (curx.bd + dt * (Ge1p - Ge0p)) + dt * (Gf1p - Gf0p);
+        }
+        const int q = h - GB;
+        if (active && q >= o0 && q < o1) {
+            const long long cq = base + (long long)q * sd;
+            bout[E * N + cq] = T_IS_E ? nT0 : nX0;
+            bout[F * N + cq] = T_IS_E ? nX0 : nT0;
+            bout[D * N + cq] = nD;
+        }
+        t0.G5 = Gt0;
+        t1.G5 = Gt1;
+        x0.G5 = Gx0;
+        x1.G5 = Gx1;
+        // ---- fluid update (as in fluid_march) of head p = h - 5 on the new field
+        if (h >= o0 - GF + GB + 1) {
+            const T bT = T(0.5) * (pT0 + pT1), bX = T(0.5) * (pX0 + pX1);
+            T bh[3] = {T(0.5) * (pD + nD), T_IS_E ? bT : bX, T_IS_E ? bX : bT};
+            const T uh[5] = {rh[GB], mh[GB], curx.me, curx.mf, curx.en};
+            const T keep[5] = {P.u3[0], P.u3[1], P.u3[2], P.u3[3], P.u3[4]};
+            const T bo[3] = {P.b3[0], P.b3[1], P.b3[2]};
+            T un[5];
+            P.push(uh, bh, gamma, dt, un);
+            const int o = h - GB - 1 - GF;
+            if (active && o >= o0) {
+                if (frozen) {
+#pragma unroll
+                    for (int k = 0; k < 5; k++) un[k] = keep[k];
+                }
+                const long long co = base + (long long)o * sd;
+                uout[co] = un[0];
+                uout[(1 + D) * N + co] = un[1];
+                uout[(1 + E) * N + co] = un[2];
+                uout[(1 + F) * N + co] = un[3];
+                uout[4 * N + co] = un[4];
+                if constexpr (CFL) {
+                    const T cc = cfl_speed(un[0], un[1 + (3 - D) % 3], un[1 + (4 - D) % 3], un[1 + (5 - D) % 3],
+                                           un[4], bo[(3 - D) % 3], bo[(4 - D) % 3], bo[(5 - D) % 3], gamma);
+                    const unsigned long long bits = speed_bits(cc);
+                    best = bits > best ? bits : best;
+                }
+            }
+        }
+        pD = nD;
+        pT0 = nT0;
+        pT1 = nT1;
+        pX0 = nX0;
+        pX1 = nX1;
+#pragma unroll
+        for (int k = GB; k > 0; k--) {
+            rh[k] = rh[k - 1];
+            mh[k] = mh[k - 1];
+        }
+        rh[0] = r0;
+        mh[0] = m0;
+        cur = nxt;
+        curx = nxtx;
+    }
+    if constexpr (CFL) block_max_to_part<64 * MW>(best, threadIdx.x + 64 * threadIdx.y, part);
+}
+
+template <typename T, int D, bool CFL>
+__global__ void __launch_bounds__(64 * MW) ct_fluid_march(const T* __restrict__ uin, T* __restrict__ uout,
+                                                          const T* __restrict__ bin, T* __restrict__ bout, Grid g,
+                                                          T gamma, const Ctl* __restrict__ ctl, double dt_arg,
+                                                          int chunk, unsigned long long* __restrict__ parts,
+                                                          int* count)
+{
+    if constexpr (CFL) store_part_count(count);
+    ct_fluid_march_body<T, D, CFL>(uin, uout, bin, bout, g, gamma, ctl, dt_arg, chunk, blockIdx.x,
+                                   parts + blockIdx.x);
+}
+
+
 // Neighbours along a row held in the lanes of one wavefront: lane i receives
 // the value of lane i + 1 (lane_next) or lane i - 1 (lane_prev); the end lane
 // with no source keeps its own value (it is a ghost lane either way). DPP
@@ -943,6 +1141,157 @@ static unsigned ct_x_wave_blocks(const Grid& g)
     return (unsigned)((waves + 3) / 4);
 }
 
+// Reverse L_x on periodic grids (Sec. 4.3: field update, then fluid update)
+// in one wavefront pass: the field update of ct_x_body on 64 consecutive
+// cells of a row, then the fluid update of fluid_x_body on the new field held
+// in the lanes. The new faces are valid on lanes 4 .. 59; the fluid update of
+// lane L reads the centred field on lanes L - 3 .. L + 3 (B_x up to L + 4), so
+// lanes 7 .. 55 are stored: XWF = 49 cells per wavefront. Same expressions as
+// the two separate kernels, so the same bits; periodic wrapping makes the new
+// field of a ghost lane that of the cell it maps to.
+constexpr int XWF = 64 - 2 * GCF - 1;
+
+template <typename T, bool CFL>
+__device__ __forceinline__ void ct_fluid_x_body(const T* __restrict__ uin, T* __restrict__ uout,
+                                                const T* __restrict__ bin, T* __restrict__ bout, const Grid& g,
+                                                T gamma, const Ctl* __restrict__ ctl, double dt_arg, unsigned lb,
+                                                unsigned long long* __restrict__ part)
+{
+    const int lane = threadIdx.x & 63;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const unsigned wpr = (unsigned)(nx + XWF - 1) / XWF;
+    const unsigned nrows = (unsigned)ny * (unsigned)nz;
+    const unsigned wave = lb * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned row = wave / wpr;
+    const int seg = (int)(wave - row * wpr);
+    const bool live = row < nrows;        // wavefronts past the last row only join the block reduction
+    const unsigned rowc = live ? row : 0u;
+    const int j = (int)(rowc % (unsigned)ny), k = (int)(rowc / (unsigned)ny);
+    const int xu = seg * XWF - GCF + lane;
+    const int x = wrap_idx(xu, nx, g.bc);
+    const int jm = wrap_idx(j - 1, ny, g.bc), jp = wrap_idx(j + 1, ny, g.bc);
+    const int km = wrap_idx(k - 1, nz, g.bc), kp = wrap_idx(k + 1, nz, g.bc);
+    const long long N = g.N;
+    const long long c = (long long)nx * (j + (long long)ny * k) + x;
+    const long long cym = (long long)nx * (jm + (long long)ny * k) + x;
+    const long long cyp = (long long)nx * (jp + (long long)ny * k) + x;
+    const long long czm = (long long)nx * (j + (long long)ny * km) + x;
+    const long long czp = (long long)nx * (j + (long long)ny * kp) + x;
+    const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
+    const bool frozen = ctl->status != 0;
+    constexpr bool kDpp = kExact<T>;
+
+    // ---- field update (as in ct_x_body)
+    T vh[4], Bk[4];
+    const T r0 = uin[c], m0 = uin[N + c];
+    vh[0] = qdiv(uin[N + cym] + m0, uin[cym] + r0);
+    vh[1] = qdiv(m0 + uin[N + cyp], r0 + uin[cyp]);
+    vh[2] = qdiv(uin[N + czm] + m0, uin[czm] + r0);
+    vh[3] = qdiv(m0 + uin[N + czp], r0 + uin[czp]);
+    Bk[0] = bin[N + c];
+    Bk[1] = bin[N + cyp];
+    Bk[2] = bin[2 * N + c];
+    Bk[3] = bin[2 * N + czp];
+    const T bx = bin[c];
+    T u[5];
+    u[0] = r0;
+    u[1] = m0;
+    u[2] = uin[2 * N + c];
+    u[3] = uin[3 * N + c];
+    u[4] = uin[4 * N + c];
+    T G[4], gm[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        const T vv = T(0.25) * (lane_prev<false>(vh[e]) + T(2) * vh[e] + lane_next<false>(vh[e]));
+        const T qb = vv * Bk[e];
+        const T ev = T(0.5) * (vv + lane_next<false>(vv));
+        const T qbn = lane_next<false>(qb);
+        const T g1 = ev > T(0) ? qb : qbn;
+        const T bhalf = Bk[e] - (dt * T(0.5)) * (g1 - lane_prev<false>(g1));
+        const T qh = vv * bhalf;
+        const T qhm = lane_prev<false>(qh), qhp = lane_next<false>(qh);
+        const T sq = vanleer_half(qh - qhm, qhp - qh);
+        const T sqp = lane_next<false>(sq);
+        G[e] = ev > T(0) ? qh + sq : qhp - sqp;
+        gm[e] = lane_prev<false>(G[e]);
+    }
+    // new faces: B_y, B_z of this row and of the +y / +z rows, B_x
+    T nB[5];   // B_x, B_y, B_y(+y), B_z, B_z(+z)
+    if (frozen) {
+        nB[0] = bx;
+        nB[1] = Bk[0];
+        nB[2] = Bk[1];
+        nB[3] = Bk[2];
+        nB[4] = Bk[3];
+    } else {
+        nB[1] = Bk[0] - dt * (G[0] - gm[0]);
+        nB[2] = Bk[1] - dt * (G[1] - gm[1]);
+        nB[3] = Bk[2] - dt * (G[2] - gm[2]);
+        nB[4] = Bk[3] - dt * (G[3] - gm[3]);
+        nB[0] = (bx + dt * (gm[1] - gm[0])) + dt * (gm[3] - gm[2]);
+    }
+    const bool store = live && lane >= GCF && lane < GCF + XWF && xu < nx;
+    if (store) {
+        bout[c] = nB[0];
+        bout[N + c] = nB[1];
+        bout[2 * N + c] = nB[3];
+    }
+    // ---- fluid update (as in fluid_x_body) on the new field
+    T b[3], rr[5], ll[5];
+    b[0] = T(0.5) * (nB[0] + lane_next<kDpp>(nB[0]));
+    b[1] = T(0.5) * (nB[1] + nB[2]);
+    b[2] = T(0.5) * (nB[3] + nB[4]);
+    movers(u, b, gamma, rr, ll);
+    T f[5], uh[5], rp[5], lp[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) f[q] = rr[q] - lane_next<kDpp>(ll[q]);
+#pragma unroll
+    for (int q = 0; q < 5; q++) uh[q] = u[q] - (dt * T(0.5)) * (f[q] - lane_prev<kDpp>(f[q]));
+    movers(uh, b, gamma, rp, lp);
+    T Rr[5], Ll[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+        const T a = lane_prev<kDpp>(rp[q]), c0 = rp[q], d = lane_next<kDpp>(rp[q]);
+        Rr[q] = c0 + vanleer_half(c0 - a, d - c0);
+        const T al = lane_prev<kDpp>(lp[q]), cl = lp[q], dl = lane_next<kDpp>(lp[q]);
+        Ll[q] = cl - vanleer_half(cl - al, dl - cl);
+    }
+    T fp[5], un[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) fp[q] = Rr[q] - lane_next<kDpp>(Ll[q]);
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+        const T fm = lane_prev<kDpp>(fp[q]);
+        un[q] = frozen ? u[q] : u[q] - dt * (fp[q] - fm);
+    }
+    unsigned long long best = 0ull;
+    if (store) {
+#pragma unroll
+        for (int q = 0; q < 5; q++) uout[q * N + c] = un[q];
+        if constexpr (CFL) {
+            const T cc = cfl_speed(un[0], un[1], un[2], un[3], un[4], b[0], b[1], b[2], gamma);
+            best = speed_bits(cc);
+        }
+    }
+    if constexpr (CFL) block_max_to_part<256>(best, threadIdx.x, part);
+}
+
+template <typename T, bool CFL>
+__global__ void __launch_bounds__(256) ct_fluid_x_wave(const T* __restrict__ uin, T* __restrict__ uout,
+                                                       const T* __restrict__ bin, T* __restrict__ bout, Grid g,
+                                                       T gamma, const Ctl* __restrict__ ctl, double dt_arg,
+                                                       unsigned long long* __restrict__ parts, int* count)
+{
+    if constexpr (CFL) store_part_count(count);
+    ct_fluid_x_body<T, CFL>(uin, uout, bin, bout, g, gamma, ctl, dt_arg, blockIdx.x, parts + blockIdx.x);
+}
+
+static unsigned ct_fluid_x_blocks(const Grid& g)
+{
+    const long long waves = (long long)g.n[1] * g.n[2] * ((g.n[0] + XWF - 1) / XWF);
+    return (unsigned)((waves + 3) / 4);
+}
+
 // ---------------------------------------------------------------------------
 constexpr int RB = 256;   // threads per block of the reductions
 
@@ -1106,6 +1455,54 @@ hipError_t launch_fluid(int axis, const T* u_in, T* u_out, const T* b, Grid g, d
         fluid_launch<T, true>(axis, u_in, u_out, b, g, gamma, ctl, dt, parts, s);
     else
         fluid_launch<T, false>(axis, u_in, u_out, b, g, gamma, ctl, dt, nullptr, s);
+    return hipGetLastError();
+}
+
+// Wavefronts per fused (field + fluid) march launch: the FP64 march runs one
+// wavefront per SIMD (its pipelines need every register), so one wavefront per
+// SIMD in a single round (256-cell chunks at 256^3; 4 % faster than two
+// rounds of 128-cell chunks); FP32 runs two per SIMD.
+template <typename T>
+constexpr long long kFusedMarchWaves = kExact<T> ? 1024 : 2048;
+
+template <typename T>
+static int fused_chunk(const Grid& g, int axis)
+{
+    return march_chunk(g, axis, GCF, kFusedMarchWaves<T>, true);
+}
+
+template <typename T>
+hipError_t launch_ct_fluid(int axis, const T* u_in, T* u_out, const T* b_in, T* b_out, Grid g, double gamma,
+                           Ctl* ctl, double dt, unsigned long long* parts, hipStream_t s)
+{
+    if (axis < 0 || axis > 2 || g.bc != 0) return hipErrorInvalidValue;
+    if (axis == 0) {
+        const unsigned nb = ct_fluid_x_blocks(g);
+        if (parts)
+            hipLaunchKernelGGL((ct_fluid_x_wave<T, true>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in, b_out, g,
+                               (T)gamma, ctl, dt, parts, &ctl->nparts);
+        else
+            hipLaunchKernelGGL((ct_fluid_x_wave<T, false>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in, b_out, g,
+                               (T)gamma, ctl, dt, nullptr, nullptr);
+        return hipGetLastError();
+    }
+    const int chunk = fused_chunk<T>(g, axis);
+    const dim3 grid(march_blocks(g, axis, chunk, kMarchXWide<T, true>)), block(64, MW);
+    if (parts) {
+        if (axis == 1)
+            hipLaunchKernelGGL((ct_fluid_march<T, 1, true>), grid, block, 0, s, u_in, u_out, b_in, b_out, g, (T)gamma,
+                               ctl, dt, chunk, parts, &ctl->nparts);
+        else
+            hipLaunchKernelGGL((ct_fluid_march<T, 2, true>), grid, block, 0, s, u_in, u_out, b_in, b_out, g, (T)gamma,
+                               ctl, dt, chunk, parts, &ctl->nparts);
+    } else {
+        if (axis == 1)
+            hipLaunchKernelGGL((ct_fluid_march<T, 1, false>), grid, block, 0, s, u_in, u_out, b_in, b_out, g,
+                               (T)gamma, ctl, dt, chunk, nullptr, nullptr);
+        else
+            hipLaunchKernelGGL((ct_fluid_march<T, 2, false>), grid, block, 0, s, u_in, u_out, b_in, b_out, g,
+                               (T)gamma, ctl, dt, chunk, nullptr, nullptr);
+    }
     return hipGetLastError();
 }
 

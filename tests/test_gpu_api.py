@@ -131,7 +131,7 @@ def test_argument_errors(B):
         with pytest.raises(B.MHDError):
             B.mhd_set_time(sv.h, float("inf"), 0)
         with pytest.raises(B.MHDError):
-            B.mhd_timing_read(sv.h, 9)
+            B.mhd_timing_read(sv.h, B.MHD_K_COUNT)
 
 
 def test_oversize_allocation_reports_oom(B):
@@ -187,12 +187,14 @@ def test_step_dt_matches_oracle(B, orc):
     # per step: the dt rule (the first step also runs a standalone c_max
     # pass; later steps take the maxima the last fluid sweep stored) and two
     # launches of each directional sub-operation
-    ((40, 30, 20), [4, 6, 6, 6, 6, 6, 6]),
-    # fluid sweeps along an axis of one cell are skipped; where the skipped
-    # pair would have produced the c_max maxima (sweep orders starting with
-    # that axis: z at s = 1, y at s = 2) a standalone pass produces them
-    ((40, 30, 1), [5, 6, 6, 0, 6, 6, 6]),
-    ((40, 1, 1), [6, 6, 0, 0, 6, 6, 6]),
+    # (periodic: each reverse L_d runs as one fused launch)
+    ((40, 30, 20), [4, 3, 3, 3, 3, 3, 3, 3, 3, 3]),
+    # fluid sweeps along an axis of one cell are skipped (and not fused);
+    # where the skipped pair would have produced the c_max maxima (sweep
+    # orders starting with that axis: z at s = 1, y at s = 2) a standalone
+    # pass produces them
+    ((40, 30, 1), [5, 3, 3, 0, 3, 3, 6, 3, 3, 0]),
+    ((40, 1, 1), [6, 3, 0, 0, 3, 6, 6, 3, 0, 0]),
 ])
 def test_timing_counts_launches(B, shape, want):
     nx, ny, nz = shape
@@ -367,3 +369,33 @@ def test_graph_replay_reduces_the_slots_of_the_last_producer(B):
                                                 [(w1, t1, 4), (w2, t2, 8), (w3, t3, 13)]):
         assert st == sw and t == tw, (st, sw, t, tw)
         assert np.array_equal(state, want)
+
+
+@pytest.mark.parametrize("shape", [(40, 36, 33), (70, 3, 29), (33, 29, 2), (64, 64, 64), (20, 130, 7),
+                                   (150, 5, 6), (5, 7, 9), (98, 1, 12)])
+def test_fused_reverse_sweeps_equal_two_launches(B, shape):
+    """The reverse L_d of a periodic grid as one fused launch against the
+    field and fluid launches one after the other: identical states, times and
+    c_max (the fused launch of the last reverse sweep also stores the c_max
+    slots) after steps in all three sweep orders, in both precisions; shapes
+    with ragged tiles and axes shorter than the stencil's reach."""
+    import torch
+
+    nx, ny, nz = shape
+    s = P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 900 + nx + ny)
+    stream = torch.cuda.Stream()
+    note("fused reverse sweeps %s" % (shape,))
+    for dtype in (B.MHD_F64, B.MHD_F32):
+        res = []
+        for fusion in (True, False):
+            with B.Solver(nx, ny, nz, H.GAMMA53, 0, dtype) as sv:
+                B.mhd_set_stream(sv.h, stream)
+                B.mhd_set_fusion(sv.h, fusion)
+                sv.set_state(s)
+                sv.step(2)
+                a = sv.get_state()
+                sv.step(2)
+                res.append((a, sv.get_state(), sv.time(), B.mhd_cmax(sv.h)))
+        (a1, b1, t1, c1), (a2, b2, t2, c2) = res
+        assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+        assert t1 == t2 and c1 == c2

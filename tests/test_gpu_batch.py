@@ -174,7 +174,7 @@ def test_batch_autotune_keeps_results(B, dtype):
         bt.autotune(2)
         for pid, (s, gm, bc) in zip(ids, probs):
             nz, ny, nx = s.shape[1:]
-            for kind in range(1, B.MHD_K_COUNT):
+            for kind in range(1, B.MHD_K_CT_Z + 1):
                 p0, p1 = B.mhd_batch_tile(bt.b, pid, kind)
                 if kind in (B.MHD_K_FLUID_X, B.MHD_K_CT_X):
                     assert (p0, p1) == (0, 0)   # a single shape along x
