@@ -75,6 +75,7 @@ size_t reduce_capacity(const Grid& g)
     size_t cap = (size_t)reduce_blocks(g);
     cap = std::max(cap, (size_t)x_wave_blocks(g));
     cap = std::max(cap, (size_t)ct_fluid_x_blocks(g));
+    cap = std::max(cap, (size_t)g.n[1] * (size_t)g.n[2]);   // row form of the fused x sweep (FP64)
     for (int axis = 1; axis <= 2; axis++) {
         cap = std::max(cap, (size_t)march_blocks(g, axis, march_chunk(g, axis, GF, kFluidMarchWaves, true), true));
         for (int c : {fused_chunk<double>(g, axis), fused_chunk<float>(g, axis)})

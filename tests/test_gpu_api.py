@@ -372,7 +372,9 @@ def test_graph_replay_reduces_the_slots_of_the_last_producer(B):
 
 
 @pytest.mark.parametrize("shape", [(40, 36, 33), (70, 3, 29), (33, 29, 2), (64, 64, 64), (20, 130, 7),
-                                   (150, 5, 6), (5, 7, 9), (98, 1, 12)])
+                                   (150, 5, 6), (5, 7, 9), (98, 1, 12),
+                                   # rows of 64 k cells: the row form of the fused x sweep (k = 1 .. 8)
+                                   (128, 20, 12), (192, 9, 7), (256, 5, 3), (64, 1, 30), (512, 3, 2)])
 def test_fused_reverse_sweeps_equal_two_launches(B, shape):
     """The reverse L_d of a periodic grid as one fused launch against the
     field and fluid launches one after the other: identical states, times and
