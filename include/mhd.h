@@ -87,10 +87,12 @@ int mhd_set_stream(mhd_t* h, void* stream);
 int mhd_set_graphs(mhd_t* h, int enable);
 
 /* Run each reverse L_d of a periodic grid (field update, then fluid update,
- * Sec. 4.3) as one launch that keeps the new field in registers (enable = 1,
- * the default), or as two launches (0). Results are identical either way;
- * grids with outflow boundaries always take two launches. */
-int mhd_set_fusion(mhd_t* h, int enable);
+ * Sec. 4.3) as one launch that keeps the new field on the chip: mode 1 (the
+ * default) where that is the faster form for the grid (always along x; along
+ * y and z where the grid is large enough for long marching chunks), 2 on every
+ * axis, 0 never (two launches). Results are identical in every mode; grids
+ * with outflow boundaries always take two launches. */
+int mhd_set_fusion(mhd_t* h, int mode);
 
 /* Copy a state in (layout above) from host memory or from device memory
  * (step 3 of the program flow of Sec. 4.2: the initial u and face B to

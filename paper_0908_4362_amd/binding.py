@@ -149,8 +149,9 @@ def mhd_set_graphs(h, enable: bool):
     _check(lib().mhd_set_graphs(h, 1 if enable else 0))
 
 
-def mhd_set_fusion(h, enable: bool):
-    _check(lib().mhd_set_fusion(h, 1 if enable else 0))
+def mhd_set_fusion(h, mode):
+    """mode: 0 / False never, 1 / True where faster (default), 2 wherever it applies."""
+    _check(lib().mhd_set_fusion(h, int(mode)))
 
 
 def mhd_set_state(h, host_state: np.ndarray):

@@ -41,7 +41,7 @@ struct mhd_solver {
     bool bound;           // buffers live in a caller-owned workspace (mhd_bind_workspace)
     // full steps replayed from HIP graphs, one per sweep order (s mod 3)
     bool graphs;
-    bool fusion;          // reverse L_d as one fused launch where it applies
+    int fusion;           // reverse L_d as one launch: 0 never, 1 where faster, 2 wherever it applies
     hipGraphExec_t exec[3];
     double exec_cfl[3];
     // optional per-kernel timing with HIP events on the handle's stream
@@ -177,10 +177,13 @@ int ct_fluid(mhd_solver* h, int axis, double dt, bool with_cfl)
 }
 
 // The fused launch covers reverse L_d of a periodic grid whose fluid sweep
-// along d runs (more than one cell).
+// along d runs (more than one cell), where it is the faster form.
 bool fused_reverse(const mhd_solver* h, int axis)
 {
-    return h->fusion && h->g.bc == MHD_BC_PERIODIC && h->g.n[axis] > 1;
+    if (!h->fusion || h->g.bc != MHD_BC_PERIODIC || h->g.n[axis] == 1) return false;
+    if (h->fusion == 2) return true;
+    return h->dtype == MHD_F64 ? mhd::fused_reverse_pays<double>(h->g, axis)
+                               : mhd::fused_reverse_pays<float>(h->g, axis);
 }
 
 // The 12 sub-operations of one full step with sweep-order index s
@@ -428,7 +431,7 @@ int mhd_create(int nx, int ny, int nz, double gamma, int bc, int dtype, mhd_t** 
     h->cmax_valid = false;
     h->bound = false;
     h->graphs = true;
-    h->fusion = true;
+    h->fusion = 1;
     for (int q = 0; q < 3; q++) {
         h->exec[q] = nullptr;
         h->exec_cfl[q] = 0.0;
@@ -549,13 +552,14 @@ int mhd_set_graphs(mhd_t* h, int enable)
     return MHD_OK;
 }
 
-int mhd_set_fusion(mhd_t* h, int enable)
+int mhd_set_fusion(mhd_t* h, int mode)
 {
     if (int rc = check(h)) return rc;
+    if (mode < 0 || mode > 2) return fail(MHD_ERR_ARG, "fusion mode must be 0, 1 or 2");
     if (int rc = set_current(h)) return rc;
     HIPCHK(hipStreamSynchronize(h->stream), "stream sync");
     drop_graphs(h);   // captured with the other launch sequence
-    h->fusion = enable != 0;
+    h->fusion = mode;
     return MHD_OK;
 }
 

@@ -72,6 +72,9 @@ hipError_t launch_ct(int axis, const T* u, const T* b_in, T* b_out, Grid g, cons
 template <typename T>
 hipError_t launch_ct_fluid(int axis, const T* u_in, T* u_out, const T* b_in, T* b_out, Grid g, double gamma,
                            Ctl* ctl, double dt, unsigned long long* parts, hipStream_t s);
+// Whether the fused launch is faster than the two launches for this axis.
+template <typename T>
+bool fused_reverse_pays(const Grid& g, int axis);
 // The field sweep along axis 1 or 2 when that axis has one cell: the fixed
 // point of the marching pipeline, evaluated per cell (same results bit for
 // bit, one pass over the fields instead of a warm-up per chunk).

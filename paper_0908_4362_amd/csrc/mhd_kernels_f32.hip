@@ -18,6 +18,7 @@ template hipError_t launch_ct_flat<float>(int, const float*, const float*, float
                                            hipStream_t);
 template hipError_t launch_ct_fluid<float>(int, const float*, float*, const float*, float*, Grid, double, Ctl*, double,
                                            unsigned long long*, hipStream_t);
+template bool fused_reverse_pays<float>(const Grid&, int);
 template void tile_default<float>(const Grid&, int, int*, int*);
 template void tile_candidates<float>(const Grid&, int, std::vector<std::pair<int, int>>&);
 template unsigned tile_blocks<float>(const Grid&, int, int, int);

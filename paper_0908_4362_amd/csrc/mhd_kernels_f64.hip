@@ -95,6 +95,7 @@ template hipError_t launch_ct_flat<double>(int, const double*, const double*, do
                                            hipStream_t);
 template hipError_t launch_ct_fluid<double>(int, const double*, double*, const double*, double*, Grid, double, Ctl*, double,
                                            unsigned long long*, hipStream_t);
+template bool fused_reverse_pays<double>(const Grid&, int);
 template void tile_default<double>(const Grid&, int, int*, int*);
 template void tile_candidates<double>(const Grid&, int, std::vector<std::pair<int, int>>&);
 template unsigned tile_blocks<double>(const Grid&, int, int, int);

@@ -1706,6 +1706,18 @@ static int fused_chunk(const Grid& g, int axis)
     return march_chunk(g, axis, GCF, kFusedMarchWaves<T>, true);
 }
 
+// The fused march pays where its chunks are long: its warm-up is 15 cells per
+// chunk (against 6 and 8 for the two marches, which also run at higher
+// occupancy), so grids that need short chunks to fill the device (2D planes,
+// 128^3) run the two launches: measured fused / two launches per reverse
+// L_y in FP64 on Orszag-Tang 512^2 0.062 / 0.041 ms, 128^3 0.105 / 0.092 ms,
+// 256^3 0.565 / 0.660 ms. The fused x sweep pays on every grid.
+template <typename T>
+bool fused_reverse_pays(const Grid& g, int axis)
+{
+    return axis == 0 || fused_chunk<T>(g, axis) >= 64;
+}
+
 template <typename T>
 hipError_t launch_ct_fluid(int axis, const T* u_in, T* u_out, const T* b_in, T* b_out, Grid g, double gamma,
                            Ctl* ctl, double dt, unsigned long long* parts, hipStream_t s)
