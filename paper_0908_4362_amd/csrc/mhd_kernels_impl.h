@@ -1528,6 +1528,240 @@ static bool ct_fluid_x_row_ok(const Grid& g)
 }
 
 // ---------------------------------------------------------------------------
+// Reverse L_x on periodic rows of 64 K cells in FP32, lane-row form: one
+// wavefront holds a whole row, K cells per lane (cell x = lane + 64 s in set
+// s), so no lane is a halo lane and nothing crosses wavefronts. The x
+// neighbour of a cell is the same set's value one lane over, rotated within
+// the wavefront, except at the seam lane (63 for the next cell, 0 for the
+// previous one), which takes the adjacent set's rotated value (cyclically).
+// Same expressions as ct_fluid_x_body, so the same bits.
+template <typename T, int K>
+__device__ __forceinline__ void lrow_next(const T* v, T* out, int lane)
+{
+    T r[K];
+    const int src = (lane + 1) & 63;
+#pragma unroll
+    for (int q = 0; q < K; q++) r[q] = __shfl(v[q], src, 64);
+#pragma unroll
+    for (int q = 0; q < K; q++) out[q] = lane == 63 ? r[(q + 1) % K] : r[q];
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void lrow_prev(const T* v, T* out, int lane)
+{
+    T r[K];
+    const int src = (lane + 63) & 63;
+#pragma unroll
+    for (int q = 0; q < K; q++) r[q] = __shfl(v[q], src, 64);
+#pragma unroll
+    for (int q = 0; q < K; q++) out[q] = lane == 0 ? r[(q + K - 1) % K] : r[q];
+}
+
+template <typename T, int K, bool CFL>
+__global__ void __launch_bounds__(256) ct_fluid_x_lrow(const T* __restrict__ uin, T* __restrict__ uout,
+                                                       const T* __restrict__ bin, T* __restrict__ bout, Grid g,
+                                                       T gamma, const Ctl* __restrict__ ctl, double dt_arg,
+                                                       unsigned long long* __restrict__ parts, int* count)
+{
+    if constexpr (CFL) store_part_count(count);
+    const int lane = threadIdx.x & 63;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const unsigned nrows = (unsigned)ny * (unsigned)nz;
+    const unsigned rw = blockIdx.x * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool live = rw < nrows;         // wavefronts past the last row only join the block reduction
+    const unsigned row = live ? rw : 0u;
+    const int j = (int)(row % (unsigned)ny), k = (int)(row / (unsigned)ny);
+    const int jm = wrap_idx(j - 1, ny, g.bc), jp = wrap_idx(j + 1, ny, g.bc);
+    const int km = wrap_idx(k - 1, nz, g.bc), kp = wrap_idx(k + 1, nz, g.bc);
+    const long long N = g.N;
+    const long long rb = (long long)nx * (j + (long long)ny * k);
+    const long long rym = (long long)nx * (jm + (long long)ny * k);
+    const long long ryp = (long long)nx * (jp + (long long)ny * k);
+    const long long rzm = (long long)nx * (j + (long long)ny * km);
+    const long long rzp = (long long)nx * (j + (long long)ny * kp);
+    const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
+    const bool frozen = ctl->status != 0;
+
+    // ---- field update (as in ct_x_body), pencil by pencil
+    T u[5][K], bx[K], nB[5][K], G[4][K], gm[4][K], Bk[4][K];
+#pragma unroll
+    for (int q = 0; q < K; q++) {
+        const int x = lane + 64 * q;
+        const long long c = rb + x;
+        u[0][q] = uin[c];
+        u[1][q] = uin[N + c];
+        u[2][q] = uin[2 * N + c];
+        u[3][q] = uin[3 * N + c];
+        u[4][q] = uin[4 * N + c];
+        bx[q] = bin[c];
+        Bk[0][q] = bin[N + c];
+        Bk[1][q] = bin[N + ryp + x];
+        Bk[2][q] = bin[2 * N + c];
+        Bk[3][q] = bin[2 * N + rzp + x];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        const long long rn = e == 0 ? rym : e == 1 ? ryp : e == 2 ? rzm : rzp;
+        T vh[K];
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            const int x = lane + 64 * q;
+            const T r0 = u[0][q], m0 = u[1][q];
+            const T rn0 = uin[rn + x], mn0 = uin[N + rn + x];
+            // lower neighbour first for pencils 0 and 2, own cell first for 1 and 3
+            vh[q] = (e & 1) ? qdiv(m0 + mn0, r0 + rn0) : qdiv(mn0 + m0, rn0 + r0);
+        }
+        T vn[K], vp[K], vv[K], qb[K];
+        lrow_next<T, K>(vh, vn, lane);
+        lrow_prev<T, K>(vh, vp, lane);
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            vv[q] = T(0.25) * (vp[q] + T(2) * vh[q] + vn[q]);
+            qb[q] = vv[q] * Bk[e][q];
+        }
+        T vvn[K], qbn[K], ev[K], g1[K];
+        lrow_next<T, K>(vv, vvn, lane);
+        lrow_next<T, K>(qb, qbn, lane);
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            ev[q] = T(0.5) * (vv[q] + vvn[q]);
+            g1[q] = ev[q] > T(0) ? qb[q] : qbn[q];
+        }
+        T g1p[K], qh[K];
+        lrow_prev<T, K>(g1, g1p, lane);
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            const T bhalf = Bk[e][q] - (dt * T(0.5)) * (g1[q] - g1p[q]);
+            qh[q] = vv[q] * bhalf;
+        }
+        T qhm[K], qhp[K], sq[K], sqp[K];
+        lrow_prev<T, K>(qh, qhm, lane);
+        lrow_next<T, K>(qh, qhp, lane);
+#pragma unroll
+        for (int q = 0; q < K; q++) sq[q] = vanleer_half(qh[q] - qhm[q], qhp[q] - qh[q]);
+        lrow_next<T, K>(sq, sqp, lane);
+#pragma unroll
+        for (int q = 0; q < K; q++) G[e][q] = ev[q] > T(0) ? qh[q] + sq[q] : qhp[q] - sqp[q];
+        lrow_prev<T, K>(G[e], gm[e], lane);
+    }
+#pragma unroll
+    for (int q = 0; q < K; q++) {
+        if (frozen) {
+            nB[0][q] = bx[q];
+            nB[1][q] = Bk[0][q];
+            nB[2][q] = Bk[1][q];
+            nB[3][q] = Bk[2][q];
+            nB[4][q] = Bk[3][q];
+        } else {
+            nB[1][q] = Bk[0][q] - dt * (G[0][q] - gm[0][q]);
+            nB[2][q] = Bk[1][q] - dt * (G[1][q] - gm[1][q]);
+            nB[3][q] = Bk[2][q] - dt * (G[2][q] - gm[2][q]);
+            nB[4][q] = Bk[3][q] - dt * (G[3][q] - gm[3][q]);
+            nB[0][q] = (bx[q] + dt * (gm[1][q] - gm[0][q])) + dt * (gm[3][q] - gm[2][q]);
+        }
+        if (live) {
+            const long long c = rb + lane + 64 * q;
+            bout[c] = nB[0][q];
+            bout[N + c] = nB[1][q];
+            bout[2 * N + c] = nB[3][q];
+        }
+    }
+    // ---- fluid update (as in fluid_x_body) on the new field, set by set where no neighbour is needed
+    T bxn[K];
+    lrow_next<T, K>(nB[0], bxn, lane);
+    T b[3][K], rr[5][K], ll[5][K];
+#pragma unroll
+    for (int q = 0; q < K; q++) {
+        b[0][q] = T(0.5) * (nB[0][q] + bxn[q]);
+        b[1][q] = T(0.5) * (nB[1][q] + nB[2][q]);
+        b[2][q] = T(0.5) * (nB[3][q] + nB[4][q]);
+        T uq[5], bq[3] = {b[0][q], b[1][q], b[2][q]}, rq[5], lq[5];
+#pragma unroll
+        for (int m = 0; m < 5; m++) uq[m] = u[m][q];
+        movers(uq, bq, gamma, rq, lq);
+#pragma unroll
+        for (int m = 0; m < 5; m++) {
+            rr[m][q] = rq[m];
+            ll[m][q] = lq[m];
+        }
+    }
+    T f[5][K];
+#pragma unroll
+    for (int m = 0; m < 5; m++) {
+        T lln[K];
+        lrow_next<T, K>(ll[m], lln, lane);
+#pragma unroll
+        for (int q = 0; q < K; q++) f[m][q] = rr[m][q] - lln[q];
+    }
+    T rp[5][K], lp[5][K];
+    {
+        T uh[5][K];
+#pragma unroll
+        for (int m = 0; m < 5; m++) {
+            T fp_[K];
+            lrow_prev<T, K>(f[m], fp_, lane);
+#pragma unroll
+            for (int q = 0; q < K; q++) uh[m][q] = u[m][q] - (dt * T(0.5)) * (f[m][q] - fp_[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            T uq[5], bq[3] = {b[0][q], b[1][q], b[2][q]}, rq[5], lq[5];
+#pragma unroll
+            for (int m = 0; m < 5; m++) uq[m] = uh[m][q];
+            movers(uq, bq, gamma, rq, lq);
+#pragma unroll
+            for (int m = 0; m < 5; m++) {
+                rp[m][q] = rq[m];
+                lp[m][q] = lq[m];
+            }
+        }
+    }
+    unsigned long long best = 0ull;
+#pragma unroll
+    for (int m = 0; m < 5; m++) {
+        T a[K], d[K], al[K], dl[K], Rr[K], Ll[K], Lln[K], fp[K], fm[K];
+        lrow_prev<T, K>(rp[m], a, lane);
+        lrow_next<T, K>(rp[m], d, lane);
+        lrow_prev<T, K>(lp[m], al, lane);
+        lrow_next<T, K>(lp[m], dl, lane);
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            const T c0 = rp[m][q], cl = lp[m][q];
+            Rr[q] = c0 + vanleer_half(c0 - a[q], d[q] - c0);
+            Ll[q] = cl - vanleer_half(cl - al[q], dl[q] - cl);
+        }
+        lrow_next<T, K>(Ll, Lln, lane);
+#pragma unroll
+        for (int q = 0; q < K; q++) fp[q] = Rr[q] - Lln[q];
+        lrow_prev<T, K>(fp, fm, lane);
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            // the new state overwrites u (its old value is not needed any more)
+            u[m][q] = frozen ? u[m][q] : u[m][q] - dt * (fp[q] - fm[q]);
+            if (live) uout[m * N + rb + lane + 64 * q] = u[m][q];
+        }
+    }
+    if constexpr (CFL) {
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            const T cc = cfl_speed(u[0][q], u[1][q], u[2][q], u[3][q], u[4][q], b[0][q], b[1][q], b[2][q], gamma);
+            const unsigned long long bits = live ? speed_bits(cc) : 0ull;
+            best = bits > best ? bits : best;
+        }
+        block_max_to_part<256>(best, threadIdx.x, parts + blockIdx.x);
+    }
+}
+
+// The lane-row form applies to periodic rows of 64, 128, 192 or 256 cells in
+// FP32.
+template <typename T>
+static int ct_fluid_x_lrow_k(const Grid& g)
+{
+    if (kExact<T> || g.bc != 0 || g.n[0] % 64 != 0 || g.n[0] > 256) return 0;
+    return g.n[0] / 64;
+}
+
+// ---------------------------------------------------------------------------
 constexpr int RB = 256;   // threads per block of the reductions
 
 // Per-cell CFL speed of eq. equat_CFL; per-block maxima into parts.
@@ -1723,6 +1957,25 @@ hipError_t launch_ct_fluid(int axis, const T* u_in, T* u_out, const T* b_in, T* 
                            Ctl* ctl, double dt, unsigned long long* parts, hipStream_t s)
 {
     if (axis < 0 || axis > 2 || g.bc != 0) return hipErrorInvalidValue;
+    if (axis == 0 && ct_fluid_x_lrow_k<T>(g)) {
+        const unsigned nb = (unsigned)(((long long)g.n[1] * g.n[2] + 3) / 4);
+        const int K = ct_fluid_x_lrow_k<T>(g);
+#define MHD_LROW_LAUNCH(KK)                                                                                    \
+    if (K == KK) {                                                                                            \
+        if (parts)                                                                                            \
+            hipLaunchKernelGGL((ct_fluid_x_lrow<T, KK, true>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in,   \
+                               b_out, g, (T)gamma, ctl, dt, parts, &ctl->nparts);                            \
+        else                                                                                                  \
+            hipLaunchKernelGGL((ct_fluid_x_lrow<T, KK, false>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in,  \
+                               b_out, g, (T)gamma, ctl, dt, nullptr, nullptr);                               \
+    }
+        MHD_LROW_LAUNCH(1)
+        MHD_LROW_LAUNCH(2)
+        MHD_LROW_LAUNCH(3)
+        MHD_LROW_LAUNCH(4)
+#undef MHD_LROW_LAUNCH
+        return hipGetLastError();
+    }
     if (axis == 0 && ct_fluid_x_row_ok<T>(g)) {
         const unsigned nb = (unsigned)((long long)g.n[1] * g.n[2]);
         const dim3 block(64 * (g.n[0] / 64));
