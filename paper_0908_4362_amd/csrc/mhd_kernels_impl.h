@@ -1528,13 +1528,17 @@ static bool ct_fluid_x_row_ok(const Grid& g)
 }
 
 // ---------------------------------------------------------------------------
-// Reverse L_x on periodic rows of 64 K cells in FP32, lane-row form: one
+// x sweeps on periodic rows of 64 K cells in FP32, lane-row form: one
 // wavefront holds a whole row, K cells per lane (cell x = lane + 64 s in set
 // s), so no lane is a halo lane and nothing crosses wavefronts. The x
 // neighbour of a cell is the same set's value one lane over, rotated within
 // the wavefront, except at the seam lane (63 for the next cell, 0 for the
 // previous one), which takes the adjacent set's rotated value (cyclically).
-// Same expressions as ct_fluid_x_body, so the same bits.
+// Used for the fused reverse L_x (ct_fluid_x_lrow: 0.350 -> 0.275 ms per
+// launch at 256^3) and the field update along x (ct_x_lrow: 0.169 -> 0.119
+// ms). The fluid update alone measured 8 % slower in this form than in the
+// wavefront form (its halo costs only 6 of 64 lanes) and keeps that form.
+// Same expressions as the wavefront forms, so the same bits.
 template <typename T, int K>
 __device__ __forceinline__ void lrow_next(const T* v, T* out, int lane)
 {
@@ -1555,6 +1559,126 @@ __device__ __forceinline__ void lrow_prev(const T* v, T* out, int lane)
     for (int q = 0; q < K; q++) r[q] = __shfl(v[q], src, 64);
 #pragma unroll
     for (int q = 0; q < K; q++) out[q] = lane == 0 ? r[(q + K - 1) % K] : r[q];
+}
+
+// Row offsets and flags of one lane-row wavefront (row = wavefront index).
+struct LRowSite {
+    long long N, rb, rym, ryp, rzm, rzp;
+    int lane;
+    bool live;   // wavefronts past the last row only join the block reduction
+};
+
+__device__ __forceinline__ LRowSite lrow_site(const Grid& g)
+{
+    LRowSite S;
+    S.lane = threadIdx.x & 63;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const unsigned nrows = (unsigned)ny * (unsigned)nz;
+    const unsigned rw = blockIdx.x * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    S.live = rw < nrows;
+    const unsigned row = S.live ? rw : 0u;
+    const int j = (int)(row % (unsigned)ny), k = (int)(row / (unsigned)ny);
+    const int jm = wrap_idx(j - 1, ny, g.bc), jp = wrap_idx(j + 1, ny, g.bc);
+    const int km = wrap_idx(k - 1, nz, g.bc), kp = wrap_idx(k + 1, nz, g.bc);
+    S.N = g.N;
+    S.rb = (long long)nx * (j + (long long)ny * k);
+    S.rym = (long long)nx * (jm + (long long)ny * k);
+    S.ryp = (long long)nx * (jp + (long long)ny * k);
+    S.rzm = (long long)nx * (j + (long long)ny * km);
+    S.rzp = (long long)nx * (j + (long long)ny * kp);
+    return S;
+}
+
+// EMF pipeline E of ct_x_body on a lane row (0: B_y own, 1: B_y at +y,
+// 2: B_z own, 3: B_z at +z): the limited EMF G at x + 1/2 and gm at x - 1/2.
+template <typename T, int K, int E>
+__device__ __forceinline__ void lrow_emf(const T* __restrict__ uin, const LRowSite S, T dt, const T (&r)[K],
+                                         const T (&m)[K], const T (&Bk)[K], T (&G)[K], T (&gm)[K])
+{
+    const long long N = S.N;
+    const int lane = S.lane;
+    const long long rn = E == 0 ? S.rym : E == 1 ? S.ryp : E == 2 ? S.rzm : S.rzp;
+    T vh[K];
+#pragma unroll
+    for (int q = 0; q < K; q++) {
+        const int x = lane + 64 * q;
+        const T r0 = r[q], m0 = m[q];
+        const T rn0 = uin[rn + x], mn0 = uin[N + rn + x];
+        // lower neighbour first for pencils 0 and 2, own cell first for 1 and 3
+        vh[q] = (E & 1) ? qdiv(m0 + mn0, r0 + rn0) : qdiv(mn0 + m0, rn0 + r0);
+    }
+    T vn[K], vp[K], vv[K], qb[K];
+    lrow_next<T, K>(vh, vn, lane);
+    lrow_prev<T, K>(vh, vp, lane);
+#pragma unroll
+    for (int q = 0; q < K; q++) {
+        vv[q] = T(0.25) * (vp[q] + T(2) * vh[q] + vn[q]);
+        qb[q] = vv[q] * Bk[q];
+    }
+    T vvn[K], qbn[K], ev[K], g1[K];
+    lrow_next<T, K>(vv, vvn, lane);
+    lrow_next<T, K>(qb, qbn, lane);
+#pragma unroll
+    for (int q = 0; q < K; q++) {
+        ev[q] = T(0.5) * (vv[q] + vvn[q]);
+        g1[q] = ev[q] > T(0) ? qb[q] : qbn[q];
+    }
+    T g1p[K], qh[K];
+    lrow_prev<T, K>(g1, g1p, lane);
+#pragma unroll
+    for (int q = 0; q < K; q++) {
+        const T bhalf = Bk[q] - (dt * T(0.5)) * (g1[q] - g1p[q]);
+        qh[q] = vv[q] * bhalf;
+    }
+    T qhm[K], qhp[K], sq[K], sqp[K];
+    lrow_prev<T, K>(qh, qhm, lane);
+    lrow_next<T, K>(qh, qhp, lane);
+#pragma unroll
+    for (int q = 0; q < K; q++) sq[q] = vanleer_half(qh[q] - qhm[q], qhp[q] - qh[q]);
+    lrow_next<T, K>(sq, sqp, lane);
+#pragma unroll
+    for (int q = 0; q < K; q++) G[q] = ev[q] > T(0) ? qh[q] + sq[q] : qhp[q] - sqp[q];
+    lrow_prev<T, K>(G, gm, lane);
+}
+
+// Field update of ct_x_body on a lane row: from rho and m_x of the row (r, m)
+// and the old faces, the new faces nB = (B_x, B_y, B_y(+y), B_z, B_z(+z)).
+template <typename T, int K>
+__device__ __forceinline__ void lrow_field(const T* __restrict__ uin, const T* __restrict__ bin, const LRowSite S,
+                                           T dt, bool frozen, const T (&r)[K], const T (&m)[K], T (&nB)[5][K])
+{
+    const long long N = S.N;
+    const int lane = S.lane;
+    T bx[K], B0[K], B1[K], B2[K], B3[K];
+#pragma unroll
+    for (int q = 0; q < K; q++) {
+        const int x = lane + 64 * q;
+        bx[q] = bin[S.rb + x];
+        B0[q] = bin[N + S.rb + x];
+        B1[q] = bin[N + S.ryp + x];
+        B2[q] = bin[2 * N + S.rb + x];
+        B3[q] = bin[2 * N + S.rzp + x];
+    }
+    T G0[K], g0[K], G1[K], g1[K], G2[K], g2[K], G3[K], g3[K];
+    lrow_emf<T, K, 0>(uin, S, dt, r, m, B0, G0, g0);
+    lrow_emf<T, K, 1>(uin, S, dt, r, m, B1, G1, g1);
+    lrow_emf<T, K, 2>(uin, S, dt, r, m, B2, G2, g2);
+    lrow_emf<T, K, 3>(uin, S, dt, r, m, B3, G3, g3);
+    // (selects, not branches: a branch here made the compiler address these
+    // arrays through a stack copy)
+#pragma unroll
+    for (int q = 0; q < K; q++) {
+        const T n1 = B0[q] - dt * (G0[q] - g0[q]);
+        const T n2 = B1[q] - dt * (G1[q] - g1[q]);
+        const T n3 = B2[q] - dt * (G2[q] - g2[q]);
+        const T n4 = B3[q] - dt * (G3[q] - g3[q]);
+        const T n0 = (bx[q] + dt * (g1[q] - g0[q])) + dt * (g3[q] - g2[q]);
+        nB[0][q] = frozen ? bx[q] : n0;
+        nB[1][q] = frozen ? B0[q] : n1;
+        nB[2][q] = frozen ? B1[q] : n2;
+        nB[3][q] = frozen ? B2[q] : n3;
+        nB[4][q] = frozen ? B3[q] : n4;
+    }
 }
 
 template <typename T, int K, bool CFL>
@@ -1752,14 +1876,46 @@ __global__ void __launch_bounds__(256) ct_fluid_x_lrow(const T* __restrict__ uin
     }
 }
 
+// B_{y->x}, B_{z->x} alone on a lane row (as ct_x_body)
+template <typename T, int K>
+__global__ void __launch_bounds__(256) ct_x_lrow(const T* __restrict__ uf, const T* __restrict__ bin,
+                                                 T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
+                                                 double dt_arg)
+{
+    const LRowSite S = lrow_site(g);
+    const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
+    const bool frozen = ctl->status != 0;
+    T r[K], m[K], nB[5][K];
+#pragma unroll
+    for (int q = 0; q < K; q++) {
+        const long long c = S.rb + S.lane + 64 * q;
+        r[q] = uf[c];
+        m[q] = uf[S.N + c];
+    }
+    lrow_field<T, K>(uf, bin, S, dt, frozen, r, m, nB);
+    if (S.live) {
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            const long long c = S.rb + S.lane + 64 * q;
+            bout[c] = nB[0][q];
+            bout[S.N + c] = nB[1][q];
+            bout[2 * S.N + c] = nB[3][q];
+        }
+    }
+}
+
 // The lane-row form applies to periodic rows of 64, 128, 192 or 256 cells in
-// FP32.
+// FP32 (K = cells per lane; 0: not applicable). In FP64 the fused sweep in
+// this form needs 247-256 VGPRs and measured 0.87 ms against 0.54 for the
+// row-per-workgroup form.
 template <typename T>
-static int ct_fluid_x_lrow_k(const Grid& g)
+static int x_lrow_k(const Grid& g)
 {
     if (kExact<T> || g.bc != 0 || g.n[0] % 64 != 0 || g.n[0] > 256) return 0;
     return g.n[0] / 64;
 }
+
+static unsigned x_lrow_blocks(const Grid& g) { return (unsigned)(((long long)g.n[1] * g.n[2] + 3) / 4); }
 
 // ---------------------------------------------------------------------------
 constexpr int RB = 256;   // threads per block of the reductions
@@ -1957,9 +2113,9 @@ hipError_t launch_ct_fluid(int axis, const T* u_in, T* u_out, const T* b_in, T* 
                            Ctl* ctl, double dt, unsigned long long* parts, hipStream_t s)
 {
     if (axis < 0 || axis > 2 || g.bc != 0) return hipErrorInvalidValue;
-    if (axis == 0 && ct_fluid_x_lrow_k<T>(g)) {
-        const unsigned nb = (unsigned)(((long long)g.n[1] * g.n[2] + 3) / 4);
-        const int K = ct_fluid_x_lrow_k<T>(g);
+    if (axis == 0 && x_lrow_k<T>(g)) {
+        const unsigned nb = x_lrow_blocks(g);
+        const int K = x_lrow_k<T>(g);
 #define MHD_LROW_LAUNCH(KK)                                                                                    \
     if (K == KK) {                                                                                            \
         if (parts)                                                                                            \
@@ -2021,7 +2177,15 @@ template <typename T>
 hipError_t launch_ct(int axis, const T* u, const T* b_in, T* b_out, Grid g, const Ctl* ctl, double dt,
                      hipStream_t s)
 {
-    if (axis == 0) {
+    if (axis == 0 && x_lrow_k<T>(g)) {
+        const unsigned nb = x_lrow_blocks(g);
+        switch (x_lrow_k<T>(g)) {
+        case 1: hipLaunchKernelGGL((ct_x_lrow<T, 1>), dim3(nb), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt); break;
+        case 2: hipLaunchKernelGGL((ct_x_lrow<T, 2>), dim3(nb), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt); break;
+        case 3: hipLaunchKernelGGL((ct_x_lrow<T, 3>), dim3(nb), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt); break;
+        default: hipLaunchKernelGGL((ct_x_lrow<T, 4>), dim3(nb), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt); break;
+        }
+    } else if (axis == 0) {
         hipLaunchKernelGGL((ct_x_wave<T>), dim3(ct_x_wave_blocks(g)), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt);
     } else {
         const int chunk = march_chunk(g, axis, GB, kCtMarchWaves<T>, true);

@@ -300,3 +300,25 @@ def test_flat_axes_match_the_marching_field_sweep(B, dtype):
             want, tw = plain(B, s, gm, bc, dtype, 6)
             assert np.array_equal(bt.get_state(pid), want), s.shape
             assert bt.time(pid) == tw
+
+
+@pytest.mark.parametrize("nx", [64, 128, 192, 256])
+def test_lane_row_x_sweeps_equal_batched_wavefront_form(B, nx):
+    """A plain FP32 handle on periodic rows of 64 k cells runs the x sweeps in
+    the lane-row form (a whole row per wavefront) and the reverse L_x fused;
+    a batch runs the wavefront form of the same kernel bodies and every L_d as
+    two launches. Both must give the same bits, with fusion on and off, after
+    steps in all three sweep orders."""
+    ny, nz = 11, 6
+    s = P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 340 + nx)
+    note("lane-row x sweeps, %d x %d x %d fp32" % (nx, ny, nz))
+    with B.Batch(B.MHD_F32) as bt:
+        pid = bt.add(s, H.GAMMA53, 0)
+        bt.step(4)
+        want = bt.get_state(pid)
+    for fusion in (1, 0):
+        with B.Solver(nx, ny, nz, H.GAMMA53, 0, B.MHD_F32) as sv:
+            B.mhd_set_fusion(sv.h, fusion)
+            sv.set_state(s)
+            sv.step(4)
+            assert np.array_equal(sv.get_state(), want), fusion
