@@ -131,9 +131,17 @@ int mhd_batch_set_graphs(mhd_batch_t* b, int enable);
 int mhd_batch_autotune(mhd_batch_t* b, int reps);
 
 /* Tile parameters in use for one problem and kind (MHD_K_* of mhd.h):
- * p0 = chunk length (y/z sweeps) or workgroup count (c_max pass), 0 for the
- * x sweeps (a single shape); p1 = 0. */
+ * p0 = chunk length (y/z sweeps) or workgroup count (c_max pass); for the x
+ * sweeps 0 (64-lane wavefronts over row segments) or K = 1, 2 (FP32 periodic
+ * rows of 64 K cells held by one wavefront, K cells per lane); p1 = 0. */
 int mhd_batch_tile(mhd_batch_t* b, int id, int kind, int* p0, int* p1);
+
+/* Pin the tile of one sweep kind for every problem of this one's grid shape
+ * and boundary condition (as the autotuner would, without timing); (p0, p1)
+ * must be one of the autotuner's candidates for that grid and kind (an x
+ * sweep: 0 or, where it applies, the lane-row K), else MHD_ERR_ARG. Tiles
+ * never change results. Synchronises the batch's stream. */
+int mhd_batch_set_tile(mhd_batch_t* b, int id, int kind, int p0, int p1);
 
 #ifdef __cplusplus
 }

@@ -85,6 +85,7 @@ def lib():
             "mhd_batch_set_graphs": ([vp, i], i),
             "mhd_batch_autotune": ([vp, i], i),
             "mhd_batch_tile": ([vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i)], i),
+            "mhd_batch_set_tile": ([vp, i, i, i, i], i),
             "mhd_batch_problem_layout": ([i, i, i, i, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                                           ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], i),
             "mhd_batch_add_inplace": ([vp, i, i, i, d, i, vp, vp, ctypes.POINTER(i)], i),
@@ -358,6 +359,10 @@ def mhd_batch_set_graphs(b, enable: bool):
 
 def mhd_batch_autotune(b, reps: int = 3):
     _check(lib().mhd_batch_autotune(b, reps))
+
+
+def mhd_batch_set_tile(b, pid: int, kind: int, p0: int, p1: int = 0):
+    _check(lib().mhd_batch_set_tile(b, pid, kind, p0, p1))
 
 
 def mhd_batch_tile(b, pid: int, kind: int):

@@ -68,7 +68,7 @@ struct Cohort {
     double exec_cfl[3] = {0.0, 0.0, 0.0};
 };
 
-using ShapeKey = std::array<int, 4>;   // nx, ny, nz, kind
+using ShapeKey = std::array<int, 5>;   // nx, ny, nz, boundary condition, kind
 
 // Pinned host staging for table uploads: a slot is rewritten only after the
 // copy that last read it has completed.
@@ -105,7 +105,7 @@ struct mhd_batch {
     int next_id;
     std::map<int, Prob> probs;
     std::vector<Cohort> cohorts;
-    std::map<ShapeKey, std::pair<int, int>> tuned;   // tile per grid shape and kind
+    std::map<ShapeKey, std::pair<int, int>> tuned;   // tile per grid shape, boundary condition and kind
     Staging staging[kStaging];
     int next_staging;
     std::vector<hipGraphExec_t> dead_graphs;   // released once the stream has drained past them
@@ -134,7 +134,7 @@ int set_current(const mhd_batch* b)
 template <typename T>
 void tile_of(const mhd_batch* b, const Grid& g, int kind, int* p0, int* p1)
 {
-    auto it = b->tuned.find(ShapeKey{g.n[0], g.n[1], g.n[2], kind});
+    auto it = b->tuned.find(ShapeKey{g.n[0], g.n[1], g.n[2], g.bc, kind});
     if (it != b->tuned.end()) {
         *p0 = it->second.first;
         *p1 = it->second.second;
@@ -526,8 +526,11 @@ int read_ctl(mhd_batch* b, const Prob& p, Ctl* out)
 template <typename T>
 int autotune(mhd_batch* b, int reps)
 {
-    std::map<std::array<int, 3>, std::vector<int>> shapes;
-    for (auto& kv : b->probs) shapes[{kv.second.g.n[0], kv.second.g.n[1], kv.second.g.n[2]}].push_back(kv.first);
+    // one timing per grid shape and boundary condition (the lane-row x sweeps
+    // apply to periodic rows only)
+    std::map<std::array<int, 4>, std::vector<int>> shapes;
+    for (auto& kv : b->probs)
+        shapes[{kv.second.g.n[0], kv.second.g.n[1], kv.second.g.n[2], kv.second.g.bc}].push_back(kv.first);
     if (shapes.empty()) return MHD_OK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0), "hipEventCreate");
@@ -546,7 +549,7 @@ int autotune(mhd_batch* b, int reps)
             double best = 1e300;
             std::pair<int, int> pick = cand[0];
             for (auto& cd : cand) {
-                b->tuned[ShapeKey{g.n[0], g.n[1], g.n[2], kind}] = cd;
+                b->tuned[ShapeKey{g.n[0], g.n[1], g.n[2], g.bc, kind}] = cd;
                 if ((rc = build_tables(b, tmp))) break;
                 // copy 0 -> copy 1 (scratch between steps)
                 if ((rc = launch_kind<T>(b, tmp, kind, false, 0, 0))) break;
@@ -567,7 +570,7 @@ int autotune(mhd_batch* b, int reps)
                     pick = cd;
                 }
             }
-            b->tuned[ShapeKey{g.n[0], g.n[1], g.n[2], kind}] = pick;
+            b->tuned[ShapeKey{g.n[0], g.n[1], g.n[2], g.bc, kind}] = pick;
         }
         if (rc) break;
     }
@@ -577,6 +580,16 @@ int autotune(mhd_batch* b, int reps)
     (void)hipEventDestroy(e1);
     for (auto& c : b->cohorts) c.dirty = true;
     return rc;
+}
+
+template <typename T>
+bool tile_is_candidate(const Grid& g, int kind, int p0, int p1)
+{
+    std::vector<std::pair<int, int>> cand;
+    mhd::tile_candidates<T>(g, kind, cand);
+    for (auto& c : cand)
+        if (c.first == p0 && c.second == p1) return true;
+    return false;
 }
 
 }  // namespace
@@ -827,6 +840,23 @@ int mhd_batch_autotune(mhd_batch_t* b, int reps)
     if (int rc = set_current(b)) return rc;
     HIPCHK(hipStreamSynchronize(b->stream), "stream sync");
     return b->dtype == MHD_F64 ? autotune<double>(b, reps) : autotune<float>(b, reps);
+}
+
+int mhd_batch_set_tile(mhd_batch_t* b, int id, int kind, int p0, int p1)
+{
+    if (!b) return fail(MHD_ERR_ARG, "null batch");
+    if (kind < mhd::KIND_FLUID_X || kind > mhd::KIND_CT_Z) return fail(MHD_ERR_ARG, "not a sweep kind");
+    Prob* p = find(b, id);
+    if (!p) return fail(MHD_ERR_ARG, "unknown problem id");
+    const Grid& g = p->g;
+    const bool ok = b->dtype == MHD_F64 ? tile_is_candidate<double>(g, kind, p0, p1)
+                                        : tile_is_candidate<float>(g, kind, p0, p1);
+    if (!ok) return fail(MHD_ERR_ARG, "not a tile the autotuner would consider for this grid and kind");
+    if (int rc = set_current(b)) return rc;
+    HIPCHK(hipStreamSynchronize(b->stream), "stream sync");
+    b->tuned[ShapeKey{g.n[0], g.n[1], g.n[2], g.bc, kind}] = {p0, p1};
+    for (auto& c : b->cohorts) c.dirty = true;
+    return MHD_OK;
 }
 
 int mhd_batch_tile(mhd_batch_t* b, int id, int kind, int* p0, int* p1)

@@ -51,6 +51,8 @@ __global__ void __launch_bounds__(64 * MW) ct_march_batch(const BJob* __restrict
                         g, J.ctl, -1.0, td[j].p0, lb);
 }
 
+// x sweeps: tile p0 = 0 runs the wavefront form, p0 = K (1 or 2) the
+// lane-row form with K cells per lane (FP32 periodic rows of 64 K cells).
 template <typename T, bool CFL>
 __global__ void __launch_bounds__(256) fluid_x_batch(const BJob* __restrict__ jobs, const TileDesc* __restrict__ td,
                                                      int njobs, int iu, int ib)
@@ -59,8 +61,20 @@ __global__ void __launch_bounds__(256) fluid_x_batch(const BJob* __restrict__ jo
     const BJob& J = jobs[j];
     const Grid g = J.g;
     const unsigned lb = blockIdx.x - td[j].first;
-    fluid_x_body<T, CFL>(static_cast<const T*>(J.u[iu]), static_cast<T*>(J.u[iu ^ 1]), static_cast<const T*>(J.b[ib]),
-                         g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
+    const T* uin = static_cast<const T*>(J.u[iu]);
+    T* uout = static_cast<T*>(J.u[iu ^ 1]);
+    const T* bf = static_cast<const T*>(J.b[ib]);
+    if constexpr (!kExact<T>) {
+        if (td[j].p0 == 1) {
+            fluid_x_lrow_body<T, 1, CFL>(uin, uout, bf, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
+            return;
+        }
+        if (td[j].p0 == 2) {
+            fluid_x_lrow_body<T, 2, CFL>(uin, uout, bf, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
+            return;
+        }
+    }
+    fluid_x_body<T, CFL>(uin, uout, bf, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
 }
 
 template <typename T>
@@ -71,8 +85,28 @@ __global__ void __launch_bounds__(256) ct_x_batch(const BJob* __restrict__ jobs,
     const BJob& J = jobs[j];
     const Grid g = J.g;
     const unsigned lb = blockIdx.x - td[j].first;
-    ct_x_body<T>(static_cast<const T*>(J.u[iu]), static_cast<const T*>(J.b[ib]), static_cast<T*>(J.b[ib ^ 1]), g,
-                 J.ctl, -1.0, lb);
+    const T* uf = static_cast<const T*>(J.u[iu]);
+    const T* bin = static_cast<const T*>(J.b[ib]);
+    T* bout = static_cast<T*>(J.b[ib ^ 1]);
+    if constexpr (!kExact<T>) {
+        if (td[j].p0 == 1) {
+            ct_x_lrow_body<T, 1>(uf, bin, bout, g, J.ctl, -1.0, lb);
+            return;
+        }
+        if (td[j].p0 == 2) {
+            ct_x_lrow_body<T, 2>(uf, bin, bout, g, J.ctl, -1.0, lb);
+            return;
+        }
+    }
+    ct_x_body<T>(uf, bin, bout, g, J.ctl, -1.0, lb);
+}
+
+// Lane-row cells per lane a batched x sweep may take for this grid (0: none).
+template <typename T>
+int batch_x_lrow_k(const Grid& g)
+{
+    const int k = x_lrow_k<T>(g);
+    return k <= 2 ? k : 0;
 }
 
 template <typename T>
@@ -97,7 +131,7 @@ void tile_default(const Grid& g, int kind, int* p0, int* p1)
     switch (kind) {
     case KIND_CFL: *p0 = reduce_blocks(g); break;
     case KIND_FLUID_X:
-    case KIND_CT_X: *p0 = 0; break;   // one shape: wavefronts of 64 cells along x
+    case KIND_CT_X: *p0 = batch_x_lrow_k<T>(g); break;   // lane-row form where it applies
     case KIND_FLUID_Y: *p0 = march_chunk(g, 1, GF, kFluidMarchWaves); break;
     case KIND_FLUID_Z: *p0 = march_chunk(g, 2, GF, kFluidMarchWaves); break;
     case KIND_CT_Y: *p0 = march_chunk(g, 1, GB, kCtMarchWaves<T>); break;
@@ -106,9 +140,9 @@ void tile_default(const Grid& g, int kind, int* p0, int* p1)
 }
 
 // Candidates: march chunks of the whole pencil down to an eighth of it (never
-// shorter than twice the ghost depth, which would be mostly warm-up). The x
-// sweeps have a single shape, and the CFL pass runs only when a batch
-// changes, so both keep their default.
+// shorter than twice the ghost depth, which would be mostly warm-up); for the
+// x sweeps the wavefront and, where it applies, the lane-row form. The CFL
+// pass runs only when a batch changes and keeps its default.
 template <typename T>
 void tile_candidates(const Grid& g, int kind, std::vector<std::pair<int, int>>& out)
 {
@@ -121,7 +155,11 @@ void tile_candidates(const Grid& g, int kind, std::vector<std::pair<int, int>>& 
         out.emplace_back(a, b);
     };
     add(d0, d1);
-    if (kind == KIND_CFL || kind == KIND_FLUID_X || kind == KIND_CT_X) return;
+    if (kind == KIND_FLUID_X || kind == KIND_CT_X) {
+        add(0, 0);
+        return;
+    }
+    if (kind == KIND_CFL) return;
     const int axis = (kind == KIND_FLUID_Y || kind == KIND_CT_Y) ? 1 : 2;
     const int ghost = (kind == KIND_FLUID_Y || kind == KIND_FLUID_Z) ? GF : GB;
     const int nd = g.n[axis];
@@ -136,8 +174,8 @@ unsigned tile_blocks(const Grid& g, int kind, int p0, int p1)
 {
     switch (kind) {
     case KIND_CFL: return (unsigned)p0;
-    case KIND_FLUID_X: return x_wave_blocks(g);
-    case KIND_CT_X: return ct_x_wave_blocks(g);
+    case KIND_FLUID_X: return p0 > 0 ? x_lrow_blocks(g) : x_wave_blocks(g);
+    case KIND_CT_X: return p0 > 0 ? x_lrow_blocks(g) : ct_x_wave_blocks(g);
     case KIND_FLUID_Y: return march_blocks(g, 1, p0, kMarchXWide<T, false>);
     case KIND_CT_Y: return march_blocks(g, 1, p0, kMarchXWide<T, true>);
     case KIND_FLUID_Z: return march_blocks(g, 2, p0, kMarchXWide<T, false>);

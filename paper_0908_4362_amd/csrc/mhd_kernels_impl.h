@@ -1568,13 +1568,13 @@ struct LRowSite {
     bool live;   // wavefronts past the last row only join the block reduction
 };
 
-__device__ __forceinline__ LRowSite lrow_site(const Grid& g)
+__device__ __forceinline__ LRowSite lrow_site(const Grid& g, unsigned lb)
 {
     LRowSite S;
     S.lane = threadIdx.x & 63;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const unsigned nrows = (unsigned)ny * (unsigned)nz;
-    const unsigned rw = blockIdx.x * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned rw = lb * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     S.live = rw < nrows;
     const unsigned row = S.live ? rw : 0u;
     const int j = (int)(row % (unsigned)ny), k = (int)(row / (unsigned)ny);
@@ -1876,13 +1876,14 @@ __global__ void __launch_bounds__(256) ct_fluid_x_lrow(const T* __restrict__ uin
     }
 }
 
-// B_{y->x}, B_{z->x} alone on a lane row (as ct_x_body)
+// B_{y->x}, B_{z->x} alone on a lane row (as ct_x_body); logical workgroup
+// lb holds rows 4 lb .. 4 lb + 3.
 template <typename T, int K>
-__global__ void __launch_bounds__(256) ct_x_lrow(const T* __restrict__ uf, const T* __restrict__ bin,
-                                                 T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
-                                                 double dt_arg)
+__device__ __forceinline__ void ct_x_lrow_body(const T* __restrict__ uf, const T* __restrict__ bin,
+                                               T* __restrict__ bout, const Grid& g, const Ctl* __restrict__ ctl,
+                                               double dt_arg, unsigned lb)
 {
-    const LRowSite S = lrow_site(g);
+    const LRowSite S = lrow_site(g, lb);
     const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
     const bool frozen = ctl->status != 0;
     T r[K], m[K], nB[5][K];
@@ -1901,6 +1902,121 @@ __global__ void __launch_bounds__(256) ct_x_lrow(const T* __restrict__ uf, const
             bout[S.N + c] = nB[1][q];
             bout[2 * S.N + c] = nB[3][q];
         }
+    }
+}
+
+template <typename T, int K>
+__global__ void __launch_bounds__(256) ct_x_lrow(const T* __restrict__ uf, const T* __restrict__ bin,
+                                                 T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
+                                                 double dt_arg)
+{
+    ct_x_lrow_body<T, K>(uf, bin, bout, g, ctl, dt_arg, blockIdx.x);
+}
+
+// fluid_x alone on a lane row (as fluid_x_body); used by batches, where rows
+// of 64 and 128 cells waste a third to a half of the wavefront form's lanes.
+// With CFL the rows' largest CFL speed goes to part (all threads take part).
+template <typename T, int K, bool CFL>
+__device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* __restrict__ uout,
+                                                  const T* __restrict__ bf, const Grid& g, T gamma,
+                                                  const Ctl* __restrict__ ctl, double dt_arg, unsigned lb,
+                                                  unsigned long long* __restrict__ part)
+{
+    const LRowSite S = lrow_site(g, lb);
+    const long long N = S.N;
+    const int lane = S.lane;
+    const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
+    const bool frozen = ctl->status != 0;
+    T u[5][K], b[3][K], bx[K], bxn[K];
+#pragma unroll
+    for (int q = 0; q < K; q++) {
+        const int x = lane + 64 * q;
+        const long long c = S.rb + x;
+#pragma unroll
+        for (int m = 0; m < 5; m++) u[m][q] = uin[m * N + c];
+        bx[q] = bf[c];
+        b[1][q] = T(0.5) * (bf[N + c] + bf[N + S.ryp + x]);
+        b[2][q] = T(0.5) * (bf[2 * N + c] + bf[2 * N + S.rzp + x]);
+    }
+    lrow_next<T, K>(bx, bxn, lane);
+#pragma unroll
+    for (int q = 0; q < K; q++) b[0][q] = T(0.5) * (bx[q] + bxn[q]);
+    T rr[5][K], ll[5][K];
+#pragma unroll
+    for (int q = 0; q < K; q++) {
+        T uq[5], bq[3] = {b[0][q], b[1][q], b[2][q]}, rq[5], lq[5];
+#pragma unroll
+        for (int m = 0; m < 5; m++) uq[m] = u[m][q];
+        movers(uq, bq, gamma, rq, lq);
+#pragma unroll
+        for (int m = 0; m < 5; m++) {
+            rr[m][q] = rq[m];
+            ll[m][q] = lq[m];
+        }
+    }
+    T f[5][K];
+#pragma unroll
+    for (int m = 0; m < 5; m++) {
+        T lln[K];
+        lrow_next<T, K>(ll[m], lln, lane);
+#pragma unroll
+        for (int q = 0; q < K; q++) f[m][q] = rr[m][q] - lln[q];
+    }
+    T rp[5][K], lp[5][K];
+    {
+        T uh[5][K];
+#pragma unroll
+        for (int m = 0; m < 5; m++) {
+            T fp_[K];
+            lrow_prev<T, K>(f[m], fp_, lane);
+#pragma unroll
+            for (int q = 0; q < K; q++) uh[m][q] = u[m][q] - (dt * T(0.5)) * (f[m][q] - fp_[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            T uq[5], bq[3] = {b[0][q], b[1][q], b[2][q]}, rq[5], lq[5];
+#pragma unroll
+            for (int m = 0; m < 5; m++) uq[m] = uh[m][q];
+            movers(uq, bq, gamma, rq, lq);
+#pragma unroll
+            for (int m = 0; m < 5; m++) {
+                rp[m][q] = rq[m];
+                lp[m][q] = lq[m];
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 5; m++) {
+        T a[K], d[K], al[K], dl[K], Rr[K], Ll[K], Lln[K], fp[K], fm[K];
+        lrow_prev<T, K>(rp[m], a, lane);
+        lrow_next<T, K>(rp[m], d, lane);
+        lrow_prev<T, K>(lp[m], al, lane);
+        lrow_next<T, K>(lp[m], dl, lane);
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            const T c0 = rp[m][q], cl = lp[m][q];
+            Rr[q] = c0 + vanleer_half(c0 - a[q], d[q] - c0);
+            Ll[q] = cl - vanleer_half(cl - al[q], dl[q] - cl);
+        }
+        lrow_next<T, K>(Ll, Lln, lane);
+#pragma unroll
+        for (int q = 0; q < K; q++) fp[q] = Rr[q] - Lln[q];
+        lrow_prev<T, K>(fp, fm, lane);
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            u[m][q] = frozen ? u[m][q] : u[m][q] - dt * (fp[q] - fm[q]);
+            if (S.live) uout[m * N + S.rb + lane + 64 * q] = u[m][q];
+        }
+    }
+    if constexpr (CFL) {
+        unsigned long long best = 0ull;
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            const T cc = cfl_speed(u[0][q], u[1][q], u[2][q], u[3][q], u[4][q], b[0][q], b[1][q], b[2][q], gamma);
+            const unsigned long long bits = S.live ? speed_bits(cc) : 0ull;
+            best = bits > best ? bits : best;
+        }
+        block_max_to_part<256>(best, threadIdx.x, part);
     }
 }
 

@@ -177,7 +177,9 @@ def test_batch_autotune_keeps_results(B, dtype):
             for kind in range(1, B.MHD_K_CT_Z + 1):
                 p0, p1 = B.mhd_batch_tile(bt.b, pid, kind)
                 if kind in (B.MHD_K_FLUID_X, B.MHD_K_CT_X):
-                    assert (p0, p1) == (0, 0)   # a single shape along x
+                    # wavefront form, or the lane-row form on FP32 periodic rows of 64 or 128 cells
+                    lrow = dtype == B.MHD_F32 and bc == 0 and nx in (64, 128)
+                    assert p1 == 0 and p0 in ((0, nx // 64) if lrow else (0,))
                 else:
                     axis = 1 if kind in (B.MHD_K_FLUID_Y, B.MHD_K_CT_Y) else 2
                     assert p0 <= s.shape[3 - axis]
@@ -305,17 +307,28 @@ def test_flat_axes_match_the_marching_field_sweep(B, dtype):
 @pytest.mark.parametrize("nx", [64, 128, 192, 256])
 def test_lane_row_x_sweeps_equal_batched_wavefront_form(B, nx):
     """A plain FP32 handle on periodic rows of 64 k cells runs the x sweeps in
-    the lane-row form (a whole row per wavefront) and the reverse L_x fused;
-    a batch runs the wavefront form of the same kernel bodies and every L_d as
-    two launches. Both must give the same bits, with fusion on and off, after
-    steps in all three sweep orders."""
+    the lane-row form (a whole row per wavefront) and the reverse L_x fused; a
+    batch whose x sweeps are pinned to the wavefront form (the autotuner's
+    other candidate) runs every L_d as two launches of the wavefront-form
+    bodies. Both must give the same bits, with fusion on and off, after steps
+    in all three sweep orders; so must the batch with its default tiles (the
+    lane-row form on rows of 64 and 128 cells)."""
     ny, nz = 11, 6
     s = P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 340 + nx)
     note("lane-row x sweeps, %d x %d x %d fp32" % (nx, ny, nz))
     with B.Batch(B.MHD_F32) as bt:
         pid = bt.add(s, H.GAMMA53, 0)
         bt.step(4)
+        dflt = bt.get_state(pid)
+    with B.Batch(B.MHD_F32) as bt:
+        pid = bt.add(s, H.GAMMA53, 0)
+        B.mhd_batch_set_tile(bt.b, pid, B.MHD_K_FLUID_X, 0)
+        B.mhd_batch_set_tile(bt.b, pid, B.MHD_K_CT_X, 0)
+        with pytest.raises(B.MHDError):
+            B.mhd_batch_set_tile(bt.b, pid, B.MHD_K_CT_X, 3)   # not a candidate
+        bt.step(4)
         want = bt.get_state(pid)
+    assert np.array_equal(dflt, want)
     for fusion in (1, 0):
         with B.Solver(nx, ny, nz, H.GAMMA53, 0, B.MHD_F32) as sv:
             B.mhd_set_fusion(sv.h, fusion)
