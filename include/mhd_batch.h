@@ -15,9 +15,12 @@
  * Problems whose step counters agree modulo 3 run the same sweep order and
  * form one cohort; each cohort runs 13 launches per full step (the per-problem
  * dt rule and 12 sweeps), captured once in a HIP graph per sweep order and
- * replayed. The autotuner picks, per grid shape and y/z sweep kind, the
- * chunk length along the sweep that runs fastest on the device (x sweeps
- * have a single shape); tiles never change results.
+ * replayed. In an FP32 cohort whose members are all periodic, each reverse
+ * L_d with more than one cell along d in every member runs as one fused
+ * launch (field update, then fluid update; Sec. 4.3), 10 launches per step,
+ * with the same bits. The autotuner picks, per grid shape and sweep kind, the
+ * chunk length along y/z sweeps and the form of x sweeps that run fastest
+ * on the device; tiles never change results.
  *
  * Memory: each problem lives in one device block of
  * mhd_batch_problem_bytes(nx, ny, nz, dtype) bytes (two state copies, its
@@ -130,10 +133,11 @@ int mhd_batch_set_graphs(mhd_batch_t* b, int enable);
  * so it may be called between any two steps. */
 int mhd_batch_autotune(mhd_batch_t* b, int reps);
 
-/* Tile parameters in use for one problem and kind (MHD_K_* of mhd.h):
- * p0 = chunk length (y/z sweeps) or workgroup count (c_max pass); for the x
- * sweeps 0 (64-lane wavefronts over row segments) or K = 1, 2 (FP32 periodic
- * rows of 64 K cells held by one wavefront, K cells per lane); p1 = 0. */
+/* Tile parameters in use for one problem and kind (MHD_K_* of mhd.h, the
+ * fused reverse kinds MHD_K_CTFLUID_* included): p0 = chunk length (y/z
+ * sweeps) or workgroup count (c_max pass); for the x sweeps 0 (64-lane
+ * wavefronts over row segments) or K = 1, 2 (FP32 periodic rows of 64 K cells
+ * held by one wavefront, K cells per lane); p1 = 0. */
 int mhd_batch_tile(mhd_batch_t* b, int id, int kind, int* p0, int* p1);
 
 /* Pin the tile of one sweep kind for every problem of this one's grid shape

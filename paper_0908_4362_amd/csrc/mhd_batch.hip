@@ -59,6 +59,7 @@ struct Cohort {
     bool dirty = true;           // membership or tiles changed since the tables were built
     bool cmax_valid = false;     // members' parts hold c_max of their current state
     int parts_kind = 0;          // launch kind whose tables describe those parts
+    bool fuse[3] = {false, false, false};   // reverse L_d as one fused launch, per axis
     void* dev = nullptr;         // job table + tile tables
     size_t dev_bytes = 0;
     BJob* jobs = nullptr;
@@ -152,13 +153,15 @@ void tile_of_dyn(const mhd_batch* b, const Grid& g, int kind, int* p0, int* p1)
 }
 
 // Reduction slots a problem needs: the most workgroups any c_max-producing
-// launch (the c_max pass, a fluid sweep) can give it, over all candidate tiles.
+// launch (the c_max pass, a fluid sweep, a fused reverse sweep) can give it,
+// over all candidate tiles.
 template <typename T>
 size_t parts_capacity(const Grid& g)
 {
     size_t cap = 1;
     std::vector<std::pair<int, int>> cand;
-    for (int kind : {mhd::KIND_CFL, mhd::KIND_FLUID_X, mhd::KIND_FLUID_Y, mhd::KIND_FLUID_Z}) {
+    for (int kind : {mhd::KIND_CFL, mhd::KIND_FLUID_X, mhd::KIND_FLUID_Y, mhd::KIND_FLUID_Z, mhd::KIND_CTFLUID_X,
+                     mhd::KIND_CTFLUID_Y, mhd::KIND_CTFLUID_Z}) {
         mhd::tile_candidates<T>(g, kind, cand);
         for (auto& c : cand) cap = std::max(cap, (size_t)mhd::tile_blocks<T>(g, kind, c.first, c.second));
     }
@@ -244,6 +247,18 @@ int upload(mhd_batch* b, void* dst, const void* src, size_t bytes)
     return MHD_OK;
 }
 
+// A cohort runs reverse L_d as one fused launch (the field update, then the
+// fluid update, of the same bits as the two launches) when every member is
+// periodic with more than one cell along d, in the precisions where the fused
+// kernels are the faster form.
+bool fuse_axis(const mhd_batch* b, const std::vector<BJob>& jobs, int axis)
+{
+    if (b->dtype != MHD_F32 || jobs.empty()) return false;
+    for (const BJob& J : jobs)
+        if (J.g.bc != MHD_BC_PERIODIC || J.g.n[axis] == 1) return false;
+    return true;
+}
+
 // Job table and per-kind tile tables of a cohort, rebuilt in device memory.
 int build_tables(mhd_batch* b, Cohort& c)
 {
@@ -310,6 +325,7 @@ int build_tables(mhd_batch* b, Cohort& c)
     c.jobs = reinterpret_cast<BJob*>(base);
     for (int k = 0; k < mhd::KIND_COUNT; k++) c.td[k] = reinterpret_cast<TileDesc*>(base + jb + k * tb);
     if (int rc = upload(b, c.dev, img.data(), need)) return rc;
+    for (int a = 0; a < 3; a++) c.fuse[a] = fuse_axis(b, jobs, a);
     c.dirty = false;
     c.cmax_valid = false;
     return MHD_OK;
@@ -339,6 +355,12 @@ int sweeps(mhd_batch* b, Cohort& c, int q)
         ib ^= 1;
     }
     for (int a = 2; a >= 0; a--) {
+        if (c.fuse[p[a]]) {
+            if ((rc = launch_kind<T>(b, c, mhd::KIND_CTFLUID_X + p[a], a == 0, iu, ib))) return rc;
+            iu ^= 1;
+            ib ^= 1;
+            continue;
+        }
         if ((rc = launch_kind<T>(b, c, mhd::KIND_CT_X + p[a], false, iu, ib))) return rc;
         ib ^= 1;
         if ((rc = launch_kind<T>(b, c, mhd::KIND_FLUID_X + p[a], a == 0, iu, ib))) return rc;
@@ -388,7 +410,7 @@ int cohort_step(mhd_batch* b, Cohort& c, double cfl)
         if ((rc = sweeps<T>(b, c, q))) return rc;
     }
     c.cmax_valid = true;
-    c.parts_kind = mhd::KIND_FLUID_X + kPerm[q][0];
+    c.parts_kind = (c.fuse[kPerm[q][0]] ? mhd::KIND_CTFLUID_X : mhd::KIND_FLUID_X) + kPerm[q][0];
     c.phase = (q + 1) % 3;
     for (int id : c.ids) b->probs.at(id).s += 1;
     return MHD_OK;
@@ -527,7 +549,7 @@ template <typename T>
 int autotune(mhd_batch* b, int reps)
 {
     // one timing per grid shape and boundary condition (the lane-row x sweeps
-    // apply to periodic rows only)
+    // and the fused reverse sweeps apply to periodic grids only)
     std::map<std::array<int, 4>, std::vector<int>> shapes;
     for (auto& kv : b->probs)
         shapes[{kv.second.g.n[0], kv.second.g.n[1], kv.second.g.n[2], kv.second.g.bc}].push_back(kv.first);
@@ -544,7 +566,10 @@ int autotune(mhd_batch* b, int reps)
     for (auto& sh : shapes) {
         tmp.ids = sh.second;
         const Grid g = b->probs.at(sh.second[0]).g;
-        for (int kind = mhd::KIND_FLUID_X; kind <= mhd::KIND_CT_Z && rc == MHD_OK; kind++) {
+        for (int kind = mhd::KIND_FLUID_X; kind <= mhd::KIND_CTFLUID_Z && rc == MHD_OK; kind++) {
+            if (kind >= mhd::KIND_CTFLUID_X &&
+                (b->dtype != MHD_F32 || g.bc != MHD_BC_PERIODIC || g.n[kind - mhd::KIND_CTFLUID_X] == 1))
+                continue;
             mhd::tile_candidates<T>(g, kind, cand);
             double best = 1e300;
             std::pair<int, int> pick = cand[0];
@@ -845,7 +870,7 @@ int mhd_batch_autotune(mhd_batch_t* b, int reps)
 int mhd_batch_set_tile(mhd_batch_t* b, int id, int kind, int p0, int p1)
 {
     if (!b) return fail(MHD_ERR_ARG, "null batch");
-    if (kind < mhd::KIND_FLUID_X || kind > mhd::KIND_CT_Z) return fail(MHD_ERR_ARG, "not a sweep kind");
+    if (kind < mhd::KIND_FLUID_X || kind > mhd::KIND_CTFLUID_Z) return fail(MHD_ERR_ARG, "not a sweep kind");
     Prob* p = find(b, id);
     if (!p) return fail(MHD_ERR_ARG, "unknown problem id");
     const Grid& g = p->g;

@@ -109,6 +109,48 @@ int batch_x_lrow_k(const Grid& g)
     return k <= 2 ? k : 0;
 }
 
+// Fused reverse L_d (periodic problems only; a cohort runs them only when
+// every member is periodic): y/z as ct_fluid_march, x as ct_fluid_x_body or,
+// with p0 = K, the lane-row form.
+template <typename T, int D, bool CFL>
+__global__ void __launch_bounds__(64 * MW) ct_fluid_march_batch(const BJob* __restrict__ jobs,
+                                                                const TileDesc* __restrict__ td, int njobs, int iu,
+                                                                int ib)
+{
+    const int j = find_job(td, njobs, blockIdx.x);
+    const BJob& J = jobs[j];
+    const Grid g = J.g;
+    const unsigned lb = blockIdx.x - td[j].first;
+    ct_fluid_march_body<T, D, CFL>(static_cast<const T*>(J.u[iu]), static_cast<T*>(J.u[iu ^ 1]),
+                                   static_cast<const T*>(J.b[ib]), static_cast<T*>(J.b[ib ^ 1]), g, (T)J.gamma, J.ctl,
+                                   -1.0, td[j].p0, lb, J.parts + lb);
+}
+
+template <typename T, bool CFL>
+__global__ void __launch_bounds__(256) ct_fluid_x_batch(const BJob* __restrict__ jobs,
+                                                        const TileDesc* __restrict__ td, int njobs, int iu, int ib)
+{
+    const int j = find_job(td, njobs, blockIdx.x);
+    const BJob& J = jobs[j];
+    const Grid g = J.g;
+    const unsigned lb = blockIdx.x - td[j].first;
+    const T* uin = static_cast<const T*>(J.u[iu]);
+    T* uout = static_cast<T*>(J.u[iu ^ 1]);
+    const T* bin = static_cast<const T*>(J.b[ib]);
+    T* bout = static_cast<T*>(J.b[ib ^ 1]);
+    if constexpr (!kExact<T>) {
+        if (td[j].p0 == 1) {
+            ct_fluid_x_lrow_body<T, 1, CFL>(uin, uout, bin, bout, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
+            return;
+        }
+        if (td[j].p0 == 2) {
+            ct_fluid_x_lrow_body<T, 2, CFL>(uin, uout, bin, bout, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
+            return;
+        }
+    }
+    ct_fluid_x_body<T, CFL>(uin, uout, bin, bout, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(RB) cfl_batch(const BJob* __restrict__ jobs, const TileDesc* __restrict__ td,
                                                 int njobs, int iu, int ib)
@@ -131,11 +173,14 @@ void tile_default(const Grid& g, int kind, int* p0, int* p1)
     switch (kind) {
     case KIND_CFL: *p0 = reduce_blocks(g); break;
     case KIND_FLUID_X:
-    case KIND_CT_X: *p0 = batch_x_lrow_k<T>(g); break;   // lane-row form where it applies
+    case KIND_CT_X:
+    case KIND_CTFLUID_X: *p0 = batch_x_lrow_k<T>(g); break;   // lane-row form where it applies
     case KIND_FLUID_Y: *p0 = march_chunk(g, 1, GF, kFluidMarchWaves); break;
     case KIND_FLUID_Z: *p0 = march_chunk(g, 2, GF, kFluidMarchWaves); break;
     case KIND_CT_Y: *p0 = march_chunk(g, 1, GB, kCtMarchWaves<T>); break;
-    default: *p0 = march_chunk(g, 2, GB, kCtMarchWaves<T>); break;
+    case KIND_CT_Z: *p0 = march_chunk(g, 2, GB, kCtMarchWaves<T>); break;
+    case KIND_CTFLUID_Y: *p0 = march_chunk(g, 1, GCF, kFusedMarchWaves<T>); break;
+    default: *p0 = march_chunk(g, 2, GCF, kFusedMarchWaves<T>); break;
     }
 }
 
@@ -155,13 +200,14 @@ void tile_candidates(const Grid& g, int kind, std::vector<std::pair<int, int>>& 
         out.emplace_back(a, b);
     };
     add(d0, d1);
-    if (kind == KIND_FLUID_X || kind == KIND_CT_X) {
+    if (kind == KIND_FLUID_X || kind == KIND_CT_X || kind == KIND_CTFLUID_X) {
         add(0, 0);
         return;
     }
     if (kind == KIND_CFL) return;
-    const int axis = (kind == KIND_FLUID_Y || kind == KIND_CT_Y) ? 1 : 2;
-    const int ghost = (kind == KIND_FLUID_Y || kind == KIND_FLUID_Z) ? GF : GB;
+    const int axis = (kind == KIND_FLUID_Y || kind == KIND_CT_Y || kind == KIND_CTFLUID_Y) ? 1 : 2;
+    const int ghost = (kind == KIND_FLUID_Y || kind == KIND_FLUID_Z) ? GF
+                      : (kind == KIND_CT_Y || kind == KIND_CT_Z) ? GB : GCF;
     const int nd = g.n[axis];
     for (int div : {1, 2, 4, 8}) {
         const int c = (nd + div - 1) / div;
@@ -179,6 +225,9 @@ unsigned tile_blocks(const Grid& g, int kind, int p0, int p1)
     case KIND_FLUID_Y: return march_blocks(g, 1, p0, kMarchXWide<T, false>);
     case KIND_CT_Y: return march_blocks(g, 1, p0, kMarchXWide<T, true>);
     case KIND_FLUID_Z: return march_blocks(g, 2, p0, kMarchXWide<T, false>);
+    case KIND_CT_Z: return march_blocks(g, 2, p0, kMarchXWide<T, true>);
+    case KIND_CTFLUID_X: return p0 > 0 ? x_lrow_blocks(g) : ct_fluid_x_blocks(g);
+    case KIND_CTFLUID_Y: return march_blocks(g, 1, p0, kMarchXWide<T, true>);
     default: return march_blocks(g, 2, p0, kMarchXWide<T, true>);
     }
 }
@@ -214,6 +263,24 @@ hipError_t launch_batch(int kind, bool cfl_parts, const BJob* jobs, const TileDe
         break;
     case KIND_CT_Y: hipLaunchKernelGGL((ct_march_batch<T, 1>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib); break;
     case KIND_CT_Z: hipLaunchKernelGGL((ct_march_batch<T, 2>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib); break;
+    case KIND_CTFLUID_X:
+        if (cfl_parts)
+            hipLaunchKernelGGL((ct_fluid_x_batch<T, true>), dim3(nb), dim3(256), 0, s, jobs, td, njobs, iu, ib);
+        else
+            hipLaunchKernelGGL((ct_fluid_x_batch<T, false>), dim3(nb), dim3(256), 0, s, jobs, td, njobs, iu, ib);
+        break;
+    case KIND_CTFLUID_Y:
+        if (cfl_parts)
+            hipLaunchKernelGGL((ct_fluid_march_batch<T, 1, true>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
+        else
+            hipLaunchKernelGGL((ct_fluid_march_batch<T, 1, false>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
+        break;
+    case KIND_CTFLUID_Z:
+        if (cfl_parts)
+            hipLaunchKernelGGL((ct_fluid_march_batch<T, 2, true>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
+        else
+            hipLaunchKernelGGL((ct_fluid_march_batch<T, 2, false>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

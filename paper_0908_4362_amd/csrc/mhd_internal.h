@@ -88,7 +88,19 @@ hipError_t launch_ct_flat(int axis, const T* u, const T* b_in, T* b_out, Grid g,
 // [first, next first) holds w.
 
 // Launch kinds (numbered as the MHD_K_* timing kinds of the C ABI).
-enum { KIND_CFL = 0, KIND_FLUID_X, KIND_FLUID_Y, KIND_FLUID_Z, KIND_CT_X, KIND_CT_Y, KIND_CT_Z, KIND_COUNT };
+enum {
+    KIND_CFL = 0,
+    KIND_FLUID_X,
+    KIND_FLUID_Y,
+    KIND_FLUID_Z,
+    KIND_CT_X,
+    KIND_CT_Y,
+    KIND_CT_Z,
+    KIND_CTFLUID_X,   // reverse L_d fused (field update, then fluid update), periodic grids
+    KIND_CTFLUID_Y,
+    KIND_CTFLUID_Z,
+    KIND_COUNT
+};
 
 // One problem of a batch as the batched kernels see it.
 struct BJob {
@@ -101,8 +113,8 @@ struct BJob {
 };
 
 // Workgroups and tile parameters of one problem in one batched launch:
-// p0 = chunk length (y/z sweeps), segment length S (x sweeps) or workgroup
-// count (CFL); p1 = rows per workgroup (x sweeps).
+// p0 = chunk length (y/z sweeps), cells per lane of the lane-row form or 0
+// for the wavefront form (x sweeps), or workgroup count (CFL); p1 = 0.
 struct TileDesc {
     unsigned first;
     int p0, p1;

@@ -1681,17 +1681,18 @@ __device__ __forceinline__ void lrow_field(const T* __restrict__ uin, const T* _
     }
 }
 
+// Logical workgroup lb holds rows 4 lb .. 4 lb + 3.
 template <typename T, int K, bool CFL>
-__global__ void __launch_bounds__(256) ct_fluid_x_lrow(const T* __restrict__ uin, T* __restrict__ uout,
-                                                       const T* __restrict__ bin, T* __restrict__ bout, Grid g,
-                                                       T gamma, const Ctl* __restrict__ ctl, double dt_arg,
-                                                       unsigned long long* __restrict__ parts, int* count)
+__device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, T* __restrict__ uout,
+                                                     const T* __restrict__ bin, T* __restrict__ bout,
+                                                     const Grid& g, T gamma, const Ctl* __restrict__ ctl,
+                                                     double dt_arg, unsigned lb,
+                                                     unsigned long long* __restrict__ part)
 {
-    if constexpr (CFL) store_part_count(count);
     const int lane = threadIdx.x & 63;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const unsigned nrows = (unsigned)ny * (unsigned)nz;
-    const unsigned rw = blockIdx.x * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned rw = lb * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool live = rw < nrows;         // wavefronts past the last row only join the block reduction
     const unsigned row = live ? rw : 0u;
     const int j = (int)(row % (unsigned)ny), k = (int)(row / (unsigned)ny);
@@ -1872,8 +1873,18 @@ __global__ void __launch_bounds__(256) ct_fluid_x_lrow(const T* __restrict__ uin
             const unsigned long long bits = live ? speed_bits(cc) : 0ull;
             best = bits > best ? bits : best;
         }
-        block_max_to_part<256>(best, threadIdx.x, parts + blockIdx.x);
+        block_max_to_part<256>(best, threadIdx.x, part);
     }
+}
+
+template <typename T, int K, bool CFL>
+__global__ void __launch_bounds__(256) ct_fluid_x_lrow(const T* __restrict__ uin, T* __restrict__ uout,
+                                                       const T* __restrict__ bin, T* __restrict__ bout, Grid g,
+                                                       T gamma, const Ctl* __restrict__ ctl, double dt_arg,
+                                                       unsigned long long* __restrict__ parts, int* count)
+{
+    if constexpr (CFL) store_part_count(count);
+    ct_fluid_x_lrow_body<T, K, CFL>(uin, uout, bin, bout, g, gamma, ctl, dt_arg, blockIdx.x, parts + blockIdx.x);
 }
 
 // B_{y->x}, B_{z->x} alone on a lane row (as ct_x_body); logical workgroup

@@ -174,14 +174,14 @@ def test_batch_autotune_keeps_results(B, dtype):
         bt.autotune(2)
         for pid, (s, gm, bc) in zip(ids, probs):
             nz, ny, nx = s.shape[1:]
-            for kind in range(1, B.MHD_K_CT_Z + 1):
+            for kind in range(1, B.MHD_K_CTFLUID_Z + 1):
                 p0, p1 = B.mhd_batch_tile(bt.b, pid, kind)
-                if kind in (B.MHD_K_FLUID_X, B.MHD_K_CT_X):
+                if kind in (B.MHD_K_FLUID_X, B.MHD_K_CT_X, B.MHD_K_CTFLUID_X):
                     # wavefront form, or the lane-row form on FP32 periodic rows of 64 or 128 cells
                     lrow = dtype == B.MHD_F32 and bc == 0 and nx in (64, 128)
                     assert p1 == 0 and p0 in ((0, nx // 64) if lrow else (0,))
                 else:
-                    axis = 1 if kind in (B.MHD_K_FLUID_Y, B.MHD_K_CT_Y) else 2
+                    axis = 1 if kind in (B.MHD_K_FLUID_Y, B.MHD_K_CT_Y, B.MHD_K_CTFLUID_Y) else 2
                     assert p0 <= s.shape[3 - axis]
         bt.step(3)
         for pid, (s, gm, bc) in zip(ids, probs):
@@ -308,8 +308,8 @@ def test_flat_axes_match_the_marching_field_sweep(B, dtype):
 def test_lane_row_x_sweeps_equal_batched_wavefront_form(B, nx):
     """A plain FP32 handle on periodic rows of 64 k cells runs the x sweeps in
     the lane-row form (a whole row per wavefront) and the reverse L_x fused; a
-    batch whose x sweeps are pinned to the wavefront form (the autotuner's
-    other candidate) runs every L_d as two launches of the wavefront-form
+    batch whose x sweeps (the fused reverse one included) are pinned to the
+    wavefront form (the autotuner's other candidate) runs the wavefront-form
     bodies. Both must give the same bits, with fusion on and off, after steps
     in all three sweep orders; so must the batch with its default tiles (the
     lane-row form on rows of 64 and 128 cells)."""
@@ -324,6 +324,7 @@ def test_lane_row_x_sweeps_equal_batched_wavefront_form(B, nx):
         pid = bt.add(s, H.GAMMA53, 0)
         B.mhd_batch_set_tile(bt.b, pid, B.MHD_K_FLUID_X, 0)
         B.mhd_batch_set_tile(bt.b, pid, B.MHD_K_CT_X, 0)
+        B.mhd_batch_set_tile(bt.b, pid, B.MHD_K_CTFLUID_X, 0)
         with pytest.raises(B.MHDError):
             B.mhd_batch_set_tile(bt.b, pid, B.MHD_K_CT_X, 3)   # not a candidate
         bt.step(4)
@@ -335,3 +336,44 @@ def test_lane_row_x_sweeps_equal_batched_wavefront_form(B, nx):
             sv.set_state(s)
             sv.step(4)
             assert np.array_equal(sv.get_state(), want), fusion
+
+
+@pytest.mark.parametrize("flat", [False, True])
+def test_batch_fused_reverse_sweeps_equal_two_launches(B, flat):
+    """An FP32 cohort of periodic problems runs each reverse L_d as one fused
+    launch (field update, then fluid update) where every member has more than
+    one cell along d; a plane in the cohort keeps the two launches along its
+    short axis. Six full steps (each sweep order twice) with the default
+    tiles, then with the fused tiles pinned to the shortest chunk along y and
+    z and the wavefront form along x: every problem bitwise equal to a plain
+    solve with fusion off."""
+    shapes = [(24, 20, 18), (70, 12, 9), (64, 10, 7), (128, 6, 5), (33, 29, 3), (5, 7, 9), (18, 60, 31)]
+    if flat:
+        shapes.append((40, 36, 1))
+    probs = [P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 390 + k) for k, (nx, ny, nz) in enumerate(shapes)]
+    note("fused reverse sweeps in a batch, plane %s" % flat)
+    wants = []
+    for s in probs:
+        nz, ny, nx = s.shape[1:]
+        with B.Solver(nx, ny, nz, H.GAMMA53, 0, B.MHD_F32) as sv:
+            B.mhd_set_fusion(sv.h, 0)
+            sv.set_state(s)
+            sv.step(6)
+            wants.append((sv.get_state(), sv.time()))
+    for pin in (False, True):
+        with B.Batch(B.MHD_F32) as bt:
+            ids = [bt.add(s, H.GAMMA53, 0) for s in probs]
+            if pin:
+                for pid, s in zip(ids, probs):
+                    nz, ny, nx = s.shape[1:]
+                    B.mhd_batch_set_tile(bt.b, pid, B.MHD_K_CTFLUID_X, 0)
+                    for kind, n in ((B.MHD_K_CTFLUID_Y, ny), (B.MHD_K_CTFLUID_Z, nz)):
+                        p0, _ = B.mhd_batch_tile(bt.b, pid, kind)
+                        for c in ((n + 7) // 8, (n + 3) // 4, (n + 1) // 2):
+                            if c >= 14 and c < p0:
+                                B.mhd_batch_set_tile(bt.b, pid, kind, c)
+                                break
+            bt.step(6)
+            for pid, s, (want, tw) in zip(ids, probs, wants):
+                assert np.array_equal(bt.get_state(pid), want), (pin, s.shape)
+                assert bt.time(pid) == tw
