@@ -15,7 +15,7 @@
  * Problems whose step counters agree modulo 3 run the same sweep order and
  * form one cohort; each cohort runs 13 launches per full step (the per-problem
  * dt rule and 12 sweeps), captured once in a HIP graph per sweep order and
- * replayed. In an FP32 cohort whose members are all periodic, each reverse
+ * replayed. In a cohort whose members are all periodic, each reverse
  * L_d with more than one cell along d in every member runs as one fused
  * launch (field update, then fluid update; Sec. 4.3), 10 launches per step,
  * with the same bits. The autotuner picks, per grid shape and sweep kind, the

@@ -338,9 +338,9 @@ def test_lane_row_x_sweeps_equal_batched_wavefront_form(B, nx):
             assert np.array_equal(sv.get_state(), want), fusion
 
 
-@pytest.mark.parametrize("flat", [False, True])
-def test_batch_fused_reverse_sweeps_equal_two_launches(B, flat):
-    """An FP32 cohort of periodic problems runs each reverse L_d as one fused
+@pytest.mark.parametrize("dtype,flat", [(0, False), (0, True), (1, False)])
+def test_batch_fused_reverse_sweeps_equal_two_launches(B, dtype, flat):
+    """A cohort of periodic problems runs each reverse L_d as one fused
     launch (field update, then fluid update) where every member has more than
     one cell along d; a plane in the cohort keeps the two launches along its
     short axis. Six full steps (each sweep order twice) with the default
@@ -351,17 +351,17 @@ def test_batch_fused_reverse_sweeps_equal_two_launches(B, flat):
     if flat:
         shapes.append((40, 36, 1))
     probs = [P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 390 + k) for k, (nx, ny, nz) in enumerate(shapes)]
-    note("fused reverse sweeps in a batch, plane %s" % flat)
+    note("fused reverse sweeps in a batch, dtype %d, plane %s" % (dtype, flat))
     wants = []
     for s in probs:
         nz, ny, nx = s.shape[1:]
-        with B.Solver(nx, ny, nz, H.GAMMA53, 0, B.MHD_F32) as sv:
+        with B.Solver(nx, ny, nz, H.GAMMA53, 0, dtype) as sv:
             B.mhd_set_fusion(sv.h, 0)
             sv.set_state(s)
             sv.step(6)
             wants.append((sv.get_state(), sv.time()))
     for pin in (False, True):
-        with B.Batch(B.MHD_F32) as bt:
+        with B.Batch(dtype) as bt:
             ids = [bt.add(s, H.GAMMA53, 0) for s in probs]
             if pin:
                 for pid, s in zip(ids, probs):
