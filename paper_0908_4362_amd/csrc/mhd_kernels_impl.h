@@ -20,6 +20,7 @@
 #pragma once
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 
 #include "mhd_internal.h"
 
@@ -1539,6 +1540,16 @@ static bool ct_fluid_x_row_ok(const Grid& g)
 // ms). The fluid update alone measured 8 % slower in this form than in the
 // wavefront form (its halo costs only 6 of 64 lanes) and keeps that form.
 // Same expressions as the wavefront forms, so the same bits.
+// The seam selects take their set indices as template constants (an index
+// sequence, not a loop): with a loop index the compiler folds the select of
+// two set values, r[a] or r[b], into a select of the index followed by an
+// indexed pick among all K values, K - 1 selects more per value.
+template <typename T, int K, int SH, int... Q>
+__device__ __forceinline__ void lrow_seam(const T* r, T* out, bool seam, std::integer_sequence<int, Q...>)
+{
+    ((out[Q] = seam ? r[(Q + SH) % K] : r[Q]), ...);
+}
+
 template <typename T, int K>
 __device__ __forceinline__ void lrow_next(const T* v, T* out, int lane)
 {
@@ -1546,8 +1557,7 @@ __device__ __forceinline__ void lrow_next(const T* v, T* out, int lane)
     const int src = (lane + 1) & 63;
 #pragma unroll
     for (int q = 0; q < K; q++) r[q] = __shfl(v[q], src, 64);
-#pragma unroll
-    for (int q = 0; q < K; q++) out[q] = lane == 63 ? r[(q + 1) % K] : r[q];
+    lrow_seam<T, K, 1>(r, out, lane == 63, std::make_integer_sequence<int, K>{});
 }
 
 template <typename T, int K>
@@ -1557,8 +1567,7 @@ __device__ __forceinline__ void lrow_prev(const T* v, T* out, int lane)
     const int src = (lane + 63) & 63;
 #pragma unroll
     for (int q = 0; q < K; q++) r[q] = __shfl(v[q], src, 64);
-#pragma unroll
-    for (int q = 0; q < K; q++) out[q] = lane == 0 ? r[(q + K - 1) % K] : r[q];
+    lrow_seam<T, K, K - 1>(r, out, lane == 0, std::make_integer_sequence<int, K>{});
 }
 
 // Row offsets and flags of one lane-row wavefront (row = wavefront index).
@@ -2031,6 +2040,16 @@ __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* 
     }
 }
 
+template <typename T, int K, bool CFL>
+__global__ void __launch_bounds__(256) fluid_x_lrow(const T* __restrict__ uin, T* __restrict__ uout,
+                                                    const T* __restrict__ bf, Grid g, T gamma,
+                                                    const Ctl* __restrict__ ctl, double dt_arg,
+                                                    unsigned long long* __restrict__ parts, int* count)
+{
+    if constexpr (CFL) store_part_count(count);
+    fluid_x_lrow_body<T, K, CFL>(uin, uout, bf, g, gamma, ctl, dt_arg, blockIdx.x, parts + blockIdx.x);
+}
+
 // The lane-row form applies to periodic rows of 64, 128, 192 or 256 cells in
 // FP32 (K = cells per lane; 0: not applicable). In FP64 the fused sweep in
 // this form needs 247-256 VGPRs and measured 0.87 ms against 0.54 for the
@@ -2182,7 +2201,27 @@ static void fluid_launch(int axis, const T* u_in, T* u_out, const T* b, Grid g, 
                          double dt, unsigned long long* parts, hipStream_t s)
 {
     int* count = CFL ? &ctl->nparts : nullptr;
-    if (axis == 0) {
+    if (axis == 0 && x_lrow_k<T>(g)) {
+        const unsigned nb = x_lrow_blocks(g);
+        switch (x_lrow_k<T>(g)) {
+        case 1:
+            hipLaunchKernelGGL((fluid_x_lrow<T, 1, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl,
+                               dt, parts, count);
+            break;
+        case 2:
+            hipLaunchKernelGGL((fluid_x_lrow<T, 2, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl,
+                               dt, parts, count);
+            break;
+        case 3:
+            hipLaunchKernelGGL((fluid_x_lrow<T, 3, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl,
+                               dt, parts, count);
+            break;
+        default:
+            hipLaunchKernelGGL((fluid_x_lrow<T, 4, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl,
+                               dt, parts, count);
+            break;
+        }
+    } else if (axis == 0) {
         const unsigned nb = x_wave_blocks(g);
         hipLaunchKernelGGL((fluid_x_wave<T, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
                            parts, count);

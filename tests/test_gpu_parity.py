@@ -61,6 +61,8 @@ SUBOP_CASES = [
     ((5, 130, 3), 0),
     ((3, 4, 131), 1),
     ((600, 3, 2), 0),
+    # periodic rows of 64 k cells: the x sweeps take their row forms
+    ((128, 9, 7), 0),
 ]
 
 
@@ -303,13 +305,17 @@ def test_gpu_deterministic(B):
 
 # --------------------------------------------------------------- bitwise FP64
 
-@pytest.mark.parametrize("case", ["random_periodic", "random_outflow", "brio_wu", "orszag_tang", "blast"])
+@pytest.mark.parametrize("case", ["random_periodic", "random_outflow", "random_rows", "brio_wu", "orszag_tang",
+                                  "blast"])
 def test_fp64_path_reproduces_oracle_bitwise(B, orc, case):
     # the FP64 kernels evaluate the oracle's expressions in the same order
     # without FMA contraction, so the results agree bit for bit; in particular
     # both take the same upwind branch at the exact ties that symmetric
     # problems produce
-    if case.startswith("random"):
+    if case == "random_rows":
+        # periodic rows of 128 cells: the row forms of the x sweeps
+        s, gamma, shape, bc = P.random_smooth(128, 13, 11, seed=P.MASTER_SEED + 52), H.GAMMA53, (128, 13, 11), 0
+    elif case.startswith("random"):
         bc = 0 if case == "random_periodic" else 1
         s, gamma, shape = P.random_smooth(29, 23, 19, seed=P.MASTER_SEED + 51), H.GAMMA53, (29, 23, 19)
     elif case == "brio_wu":
