@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(256) ct_x_batch(const BJob* __restrict__ jobs,
 template <typename T>
 int batch_x_lrow_k(const Grid& g)
 {
-    const int k = x_lrow_k<T>(g);
+    const int k = kExact<T> ? 0 : x_lrow_k(g);
     return k <= 2 ? k : 0;
 }
 

@@ -1535,11 +1535,11 @@ static bool ct_fluid_x_row_ok(const Grid& g)
 // neighbour of a cell is the same set's value one lane over, rotated within
 // the wavefront, except at the seam lane (63 for the next cell, 0 for the
 // previous one), which takes the adjacent set's rotated value (cyclically).
-// Used for the fused reverse L_x (ct_fluid_x_lrow: 0.350 -> 0.275 ms per
-// launch at 256^3) and the field update along x (ct_x_lrow: 0.169 -> 0.119
-// ms). The fluid update alone measured 8 % slower in this form than in the
-// wavefront form (its halo costs only 6 of 64 lanes) and keeps that form.
-// Same expressions as the wavefront forms, so the same bits.
+// Used for the fused reverse L_x (ct_fluid_x_lrow: 0.350 -> 0.255 ms per
+// launch at 256^3), the field update along x (ct_x_lrow: 0.169 -> 0.120 ms)
+// and the fluid update along x (fluid_x_lrow: 0.187 -> 0.157 ms, against the
+// wavefront form whose 6 halo lanes of 64 update nothing). Same expressions
+// as the wavefront forms, so the same bits.
 // The seam selects take their set indices as template constants (an index
 // sequence, not a loop): with a loop index the compiler folds the select of
 // two set values, r[a] or r[b], into a select of the index followed by an
@@ -1933,8 +1933,9 @@ __global__ void __launch_bounds__(256) ct_x_lrow(const T* __restrict__ uf, const
     ct_x_lrow_body<T, K>(uf, bin, bout, g, ctl, dt_arg, blockIdx.x);
 }
 
-// fluid_x alone on a lane row (as fluid_x_body); used by batches, where rows
-// of 64 and 128 cells waste a third to a half of the wavefront form's lanes.
+// fluid_x alone on a lane row (as fluid_x_body); batches use it on rows of 64
+// and 128 cells, where the wavefront form wastes a third to a half of its
+// lanes.
 // With CFL the rows' largest CFL speed goes to part (all threads take part).
 template <typename T, int K, bool CFL>
 __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* __restrict__ uout,
@@ -2050,15 +2051,23 @@ __global__ void __launch_bounds__(256) fluid_x_lrow(const T* __restrict__ uin, T
     fluid_x_lrow_body<T, K, CFL>(uin, uout, bf, g, gamma, ctl, dt_arg, blockIdx.x, parts + blockIdx.x);
 }
 
-// The lane-row form applies to periodic rows of 64, 128, 192 or 256 cells in
-// FP32 (K = cells per lane; 0: not applicable). In FP64 the fused sweep in
-// this form needs 247-256 VGPRs and measured 0.87 ms against 0.54 for the
-// row-per-workgroup form.
-template <typename T>
+// Cells per lane of the lane-row form on periodic rows of 64, 128, 192 or 256
+// cells (0: not applicable). The field update along x takes it in both
+// precisions (FP64 256^3: 0.303 -> 0.254 ms against the wavefront form); the
+// fluid update and the fused reverse L_x take it in FP32 only: in FP64 the
+// fluid update measured 0.379 ms against 0.357 for the wavefront form, and
+// the fused sweep needs 247-256 VGPRs in this form and runs in the
+// row-per-workgroup form instead.
 static int x_lrow_k(const Grid& g)
 {
-    if (kExact<T> || g.bc != 0 || g.n[0] % 64 != 0 || g.n[0] > 256) return 0;
+    if (g.bc != 0 || g.n[0] % 64 != 0 || g.n[0] > 256) return 0;
     return g.n[0] / 64;
+}
+
+template <typename T>
+static int x_lrow_k_fluid(const Grid& g)
+{
+    return kExact<T> ? 0 : x_lrow_k(g);
 }
 
 static unsigned x_lrow_blocks(const Grid& g) { return (unsigned)(((long long)g.n[1] * g.n[2] + 3) / 4); }
@@ -2201,9 +2210,9 @@ static void fluid_launch(int axis, const T* u_in, T* u_out, const T* b, Grid g, 
                          double dt, unsigned long long* parts, hipStream_t s)
 {
     int* count = CFL ? &ctl->nparts : nullptr;
-    if (axis == 0 && x_lrow_k<T>(g)) {
+    if (axis == 0 && x_lrow_k_fluid<T>(g)) {
         const unsigned nb = x_lrow_blocks(g);
-        switch (x_lrow_k<T>(g)) {
+        switch (x_lrow_k_fluid<T>(g)) {
         case 1:
             hipLaunchKernelGGL((fluid_x_lrow<T, 1, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl,
                                dt, parts, count);
@@ -2279,9 +2288,9 @@ hipError_t launch_ct_fluid(int axis, const T* u_in, T* u_out, const T* b_in, T* 
                            Ctl* ctl, double dt, unsigned long long* parts, hipStream_t s)
 {
     if (axis < 0 || axis > 2 || g.bc != 0) return hipErrorInvalidValue;
-    if (axis == 0 && x_lrow_k<T>(g)) {
+    if (axis == 0 && x_lrow_k_fluid<T>(g)) {
         const unsigned nb = x_lrow_blocks(g);
-        const int K = x_lrow_k<T>(g);
+        const int K = x_lrow_k_fluid<T>(g);
 #define MHD_LROW_LAUNCH(KK)                                                                                    \
     if (K == KK) {                                                                                            \
         if (parts)                                                                                            \
@@ -2343,9 +2352,9 @@ template <typename T>
 hipError_t launch_ct(int axis, const T* u, const T* b_in, T* b_out, Grid g, const Ctl* ctl, double dt,
                      hipStream_t s)
 {
-    if (axis == 0 && x_lrow_k<T>(g)) {
+    if (axis == 0 && x_lrow_k(g)) {
         const unsigned nb = x_lrow_blocks(g);
-        switch (x_lrow_k<T>(g)) {
+        switch (x_lrow_k(g)) {
         case 1: hipLaunchKernelGGL((ct_x_lrow<T, 1>), dim3(nb), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt); break;
         case 2: hipLaunchKernelGGL((ct_x_lrow<T, 2>), dim3(nb), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt); break;
         case 3: hipLaunchKernelGGL((ct_x_lrow<T, 3>), dim3(nb), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt); break;
