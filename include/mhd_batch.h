@@ -135,16 +135,20 @@ int mhd_batch_autotune(mhd_batch_t* b, int reps);
 
 /* Tile parameters in use for one problem and kind (MHD_K_* of mhd.h, the
  * fused reverse kinds MHD_K_CTFLUID_* included): p0 = chunk length (y/z
- * sweeps) or workgroup count (c_max pass); for the x sweeps 0 (64-lane
- * wavefronts over row segments) or K = 1, 2 (FP32 periodic rows of 64 K cells
- * held by one wavefront, K cells per lane); p1 = 0. */
+ * sweeps) or workgroup count (c_max pass), p1 = 0; for the x sweeps p0 = 0,
+ * p1 = 0 (64-lane wavefronts over row segments) or the lane-row form, p0 = K
+ * cells per lane and p1 = W lanes per row, on FP32 periodic rows of W K
+ * cells: (K, W) = (1, 64), (2, 64) for rows of 64 and 128 cells, each held by
+ * one wavefront; (1, 32), (3, 32) for rows of 32 and 96 cells, two to a
+ * wavefront; (3, 16) for rows of 48 cells, four to a wavefront. */
 int mhd_batch_tile(mhd_batch_t* b, int id, int kind, int* p0, int* p1);
 
 /* Pin the tile of one sweep kind for every problem of this one's grid shape
  * and boundary condition (as the autotuner would, without timing); (p0, p1)
  * must be one of the autotuner's candidates for that grid and kind (an x
- * sweep: 0 or, where it applies, the lane-row K), else MHD_ERR_ARG. Tiles
- * never change results. Synchronises the batch's stream. */
+ * sweep: (0, 0) or, where it applies, the lane-row (K, W)), else
+ * MHD_ERR_ARG. Tiles never change results. Synchronises the batch's
+ * stream. */
 int mhd_batch_set_tile(mhd_batch_t* b, int id, int kind, int p0, int p1);
 
 #ifdef __cplusplus

@@ -51,8 +51,17 @@ __global__ void __launch_bounds__(64 * MW) ct_march_batch(const BJob* __restrict
                         g, J.ctl, -1.0, td[j].p0, lb);
 }
 
-// x sweeps: tile p0 = 0 runs the wavefront form, p0 = K (1 or 2) the
-// lane-row form with K cells per lane (FP32 periodic rows of 64 K cells).
+// x sweeps: tile p0 = 0 runs the wavefront form, p0 = K with p1 = W the
+// lane-row form with K cells per lane and W lanes per row (FP32 periodic rows
+// of W K cells: 64, 128, 32, 96 and 48 cells).
+#define MHD_BATCH_LROW_DISPATCH(K, W, X) \
+    switch ((K) * 100 + (W)) {           \
+    case 164: X(1, 64) break;            \
+    case 264: X(2, 64) break;            \
+    case 132: X(1, 32) break;            \
+    case 332: X(3, 32) break;            \
+    default: X(3, 16) break;             \
+    }
 template <typename T, bool CFL>
 __global__ void __launch_bounds__(256) fluid_x_batch(const BJob* __restrict__ jobs, const TileDesc* __restrict__ td,
                                                      int njobs, int iu, int ib)
@@ -65,12 +74,11 @@ __global__ void __launch_bounds__(256) fluid_x_batch(const BJob* __restrict__ jo
     T* uout = static_cast<T*>(J.u[iu ^ 1]);
     const T* bf = static_cast<const T*>(J.b[ib]);
     if constexpr (!kExact<T>) {
-        if (td[j].p0 == 1) {
-            fluid_x_lrow_body<T, 1, CFL>(uin, uout, bf, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
-            return;
-        }
-        if (td[j].p0 == 2) {
-            fluid_x_lrow_body<T, 2, CFL>(uin, uout, bf, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
+        if (td[j].p0) {
+#define MHD_LROW_BFLUID(KK, WW) \
+    fluid_x_lrow_body<T, KK, WW, CFL>(uin, uout, bf, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
+            MHD_BATCH_LROW_DISPATCH(td[j].p0, td[j].p1, MHD_LROW_BFLUID)
+#undef MHD_LROW_BFLUID
             return;
         }
     }
@@ -89,24 +97,24 @@ __global__ void __launch_bounds__(256) ct_x_batch(const BJob* __restrict__ jobs,
     const T* bin = static_cast<const T*>(J.b[ib]);
     T* bout = static_cast<T*>(J.b[ib ^ 1]);
     if constexpr (!kExact<T>) {
-        if (td[j].p0 == 1) {
-            ct_x_lrow_body<T, 1>(uf, bin, bout, g, J.ctl, -1.0, lb);
-            return;
-        }
-        if (td[j].p0 == 2) {
-            ct_x_lrow_body<T, 2>(uf, bin, bout, g, J.ctl, -1.0, lb);
+        if (td[j].p0) {
+#define MHD_LROW_BCT(KK, WW) ct_x_lrow_body<T, KK, WW>(uf, bin, bout, g, J.ctl, -1.0, lb);
+            MHD_BATCH_LROW_DISPATCH(td[j].p0, td[j].p1, MHD_LROW_BCT)
+#undef MHD_LROW_BCT
             return;
         }
     }
     ct_x_body<T>(uf, bin, bout, g, J.ctl, -1.0, lb);
 }
 
-// Lane-row cells per lane a batched x sweep may take for this grid (0: none).
+// Lane-row cells per lane (and in *W the lanes per row) a batched x sweep may
+// take for this grid (0: none): the shapes MHD_BATCH_LROW_DISPATCH covers.
 template <typename T>
-int batch_x_lrow_k(const Grid& g)
+int batch_x_lrow_k(const Grid& g, int* W)
 {
-    const int k = kExact<T> ? 0 : x_lrow_k(g);
-    return k <= 2 ? k : 0;
+    if (kExact<T>) return 0;
+    const int k = x_lrow_k(g, W, 3);
+    return (k == 3 && *W == 64) ? 0 : k;
 }
 
 // Fused reverse L_d (periodic problems only; a cohort runs them only when
@@ -139,12 +147,11 @@ __global__ void __launch_bounds__(256) ct_fluid_x_batch(const BJob* __restrict__
     const T* bin = static_cast<const T*>(J.b[ib]);
     T* bout = static_cast<T*>(J.b[ib ^ 1]);
     if constexpr (!kExact<T>) {
-        if (td[j].p0 == 1) {
-            ct_fluid_x_lrow_body<T, 1, CFL>(uin, uout, bin, bout, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
-            return;
-        }
-        if (td[j].p0 == 2) {
-            ct_fluid_x_lrow_body<T, 2, CFL>(uin, uout, bin, bout, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
+        if (td[j].p0) {
+#define MHD_LROW_BFUSED(KK, WW) \
+    ct_fluid_x_lrow_body<T, KK, WW, CFL>(uin, uout, bin, bout, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
+            MHD_BATCH_LROW_DISPATCH(td[j].p0, td[j].p1, MHD_LROW_BFUSED)
+#undef MHD_LROW_BFUSED
             return;
         }
     }
@@ -174,7 +181,12 @@ void tile_default(const Grid& g, int kind, int* p0, int* p1)
     case KIND_CFL: *p0 = reduce_blocks(g); break;
     case KIND_FLUID_X:
     case KIND_CT_X:
-    case KIND_CTFLUID_X: *p0 = batch_x_lrow_k<T>(g); break;   // lane-row form where it applies
+    case KIND_CTFLUID_X: {   // lane-row form where it applies
+        int W = 64;
+        *p0 = batch_x_lrow_k<T>(g, &W);
+        *p1 = *p0 ? W : 0;
+        break;
+    }
     case KIND_FLUID_Y: *p0 = march_chunk(g, 1, GF, kFluidMarchWaves); break;
     case KIND_FLUID_Z: *p0 = march_chunk(g, 2, GF, kFluidMarchWaves); break;
     case KIND_CT_Y: *p0 = march_chunk(g, 1, GB, kCtMarchWaves<T>); break;
@@ -220,13 +232,13 @@ unsigned tile_blocks(const Grid& g, int kind, int p0, int p1)
 {
     switch (kind) {
     case KIND_CFL: return (unsigned)p0;
-    case KIND_FLUID_X: return p0 > 0 ? x_lrow_blocks(g) : x_wave_blocks(g);
-    case KIND_CT_X: return p0 > 0 ? x_lrow_blocks(g) : ct_x_wave_blocks(g);
+    case KIND_FLUID_X: return p0 > 0 ? x_lrow_blocks(g, p1) : x_wave_blocks(g);
+    case KIND_CT_X: return p0 > 0 ? x_lrow_blocks(g, p1) : ct_x_wave_blocks(g);
     case KIND_FLUID_Y: return march_blocks(g, 1, p0, kMarchXWide<T, false>);
     case KIND_CT_Y: return march_blocks(g, 1, p0, kMarchXWide<T, true>);
     case KIND_FLUID_Z: return march_blocks(g, 2, p0, kMarchXWide<T, false>);
     case KIND_CT_Z: return march_blocks(g, 2, p0, kMarchXWide<T, true>);
-    case KIND_CTFLUID_X: return p0 > 0 ? x_lrow_blocks(g) : ct_fluid_x_blocks(g);
+    case KIND_CTFLUID_X: return p0 > 0 ? x_lrow_blocks(g, p1) : ct_fluid_x_blocks(g);
     case KIND_CTFLUID_Y: return march_blocks(g, 1, p0, kMarchXWide<T, true>);
     default: return march_blocks(g, 2, p0, kMarchXWide<T, true>);
     }

@@ -1550,40 +1550,69 @@ __device__ __forceinline__ void lrow_seam(const T* r, T* out, bool seam, std::in
     ((out[Q] = seam ? r[(Q + SH) % K] : r[Q]), ...);
 }
 
-template <typename T, int K>
-__device__ __forceinline__ void lrow_next(const T* v, T* out, int lane)
-{
-    T r[K];
-    const int src = (lane + 1) & 63;
-#pragma unroll
-    for (int q = 0; q < K; q++) r[q] = __shfl(v[q], src, 64);
-    lrow_seam<T, K, 1>(r, out, lane == 63, std::make_integer_sequence<int, K>{});
-}
-
-template <typename T, int K>
-__device__ __forceinline__ void lrow_prev(const T* v, T* out, int lane)
-{
-    T r[K];
-    const int src = (lane + 63) & 63;
-#pragma unroll
-    for (int q = 0; q < K; q++) r[q] = __shfl(v[q], src, 64);
-    lrow_seam<T, K, K - 1>(r, out, lane == 0, std::make_integer_sequence<int, K>{});
-}
-
-// Row offsets and flags of one lane-row wavefront (row = wavefront index).
-struct LRowSite {
-    long long N, rb, rym, ryp, rzm, rzp;
-    int lane;
-    bool live;   // wavefronts past the last row only join the block reduction
+// Lanes of a lane-row wavefront: 64 / W rows of W lanes each (W = 16, 32 or
+// 64), K cells per lane; cell x of set s is xl + W s.
+template <int W>
+struct LRowLanes {
+    int xl;                      // position of the lane among its row's lanes
+    int src_next, src_prev;      // lanes holding the next / previous cell of the same set
+    bool seam_next, seam_prev;   // the neighbour is in the adjacent set instead
 };
 
-__device__ __forceinline__ LRowSite lrow_site(const Grid& g, unsigned lb)
+template <int W>
+__device__ __forceinline__ LRowLanes<W> lrow_lanes()
 {
-    LRowSite S;
-    S.lane = threadIdx.x & 63;
+    LRowLanes<W> L;
+    const int lane = threadIdx.x & 63;
+    const int first = lane & ~(W - 1);
+    L.xl = lane & (W - 1);
+    L.src_next = first | ((lane + 1) & (W - 1));
+    L.src_prev = first | ((lane + W - 1) & (W - 1));
+    L.seam_next = L.xl == W - 1;
+    L.seam_prev = L.xl == 0;
+    return L;
+}
+
+template <int W>
+__device__ __forceinline__ int lrow_x(const LRowLanes<W>& L, int q) { return L.xl + W * q; }
+
+template <typename T, int K, int W>
+__device__ __forceinline__ void lrow_next(const T* v, T* out, const LRowLanes<W>& L)
+{
+    T r[K];
+#pragma unroll
+    for (int q = 0; q < K; q++) r[q] = __shfl(v[q], L.src_next, 64);
+    lrow_seam<T, K, 1>(r, out, L.seam_next, std::make_integer_sequence<int, K>{});
+}
+
+template <typename T, int K, int W>
+__device__ __forceinline__ void lrow_prev(const T* v, T* out, const LRowLanes<W>& L)
+{
+    T r[K];
+#pragma unroll
+    for (int q = 0; q < K; q++) r[q] = __shfl(v[q], L.src_prev, 64);
+    lrow_seam<T, K, K - 1>(r, out, L.seam_prev, std::make_integer_sequence<int, K>{});
+}
+
+// Row offsets and flags of one lane of a lane-row wavefront; logical
+// workgroup lb holds rows 4 R lb .. 4 R lb + 4 R - 1 (R = 64 / W rows per
+// wavefront; with W = 64 every offset is uniform across the wavefront).
+template <int W>
+struct LRowSite {
+    long long N, rb, rym, ryp, rzm, rzp;
+    LRowLanes<W> L;
+    bool live;   // lanes past the last row only join the block reduction
+};
+
+template <int W>
+__device__ __forceinline__ LRowSite<W> lrow_site(const Grid& g, unsigned lb)
+{
+    LRowSite<W> S;
+    S.L = lrow_lanes<W>();
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const unsigned nrows = (unsigned)ny * (unsigned)nz;
-    const unsigned rw = lb * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr unsigned R = 64u / W;
+    const unsigned rw = (lb * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * R + (threadIdx.x & 63u) / W;
     S.live = rw < nrows;
     const unsigned row = S.live ? rw : 0u;
     const int j = (int)(row % (unsigned)ny), k = (int)(row / (unsigned)ny);
@@ -1600,68 +1629,68 @@ __device__ __forceinline__ LRowSite lrow_site(const Grid& g, unsigned lb)
 
 // EMF pipeline E of ct_x_body on a lane row (0: B_y own, 1: B_y at +y,
 // 2: B_z own, 3: B_z at +z): the limited EMF G at x + 1/2 and gm at x - 1/2.
-template <typename T, int K, int E>
-__device__ __forceinline__ void lrow_emf(const T* __restrict__ uin, const LRowSite S, T dt, const T (&r)[K],
+template <typename T, int K, int W, int E>
+__device__ __forceinline__ void lrow_emf(const T* __restrict__ uin, const LRowSite<W>& S, T dt, const T (&r)[K],
                                          const T (&m)[K], const T (&Bk)[K], T (&G)[K], T (&gm)[K])
 {
     const long long N = S.N;
-    const int lane = S.lane;
+    const LRowLanes<W>& L = S.L;
     const long long rn = E == 0 ? S.rym : E == 1 ? S.ryp : E == 2 ? S.rzm : S.rzp;
     T vh[K];
 #pragma unroll
     for (int q = 0; q < K; q++) {
-        const int x = lane + 64 * q;
+        const int x = lrow_x(L, q);
         const T r0 = r[q], m0 = m[q];
         const T rn0 = uin[rn + x], mn0 = uin[N + rn + x];
         // lower neighbour first for pencils 0 and 2, own cell first for 1 and 3
         vh[q] = (E & 1) ? qdiv(m0 + mn0, r0 + rn0) : qdiv(mn0 + m0, rn0 + r0);
     }
     T vn[K], vp[K], vv[K], qb[K];
-    lrow_next<T, K>(vh, vn, lane);
-    lrow_prev<T, K>(vh, vp, lane);
+    lrow_next<T, K, W>(vh, vn, L);
+    lrow_prev<T, K, W>(vh, vp, L);
 #pragma unroll
     for (int q = 0; q < K; q++) {
         vv[q] = T(0.25) * (vp[q] + T(2) * vh[q] + vn[q]);
         qb[q] = vv[q] * Bk[q];
     }
     T vvn[K], qbn[K], ev[K], g1[K];
-    lrow_next<T, K>(vv, vvn, lane);
-    lrow_next<T, K>(qb, qbn, lane);
+    lrow_next<T, K, W>(vv, vvn, L);
+    lrow_next<T, K, W>(qb, qbn, L);
 #pragma unroll
     for (int q = 0; q < K; q++) {
         ev[q] = T(0.5) * (vv[q] + vvn[q]);
         g1[q] = ev[q] > T(0) ? qb[q] : qbn[q];
     }
     T g1p[K], qh[K];
-    lrow_prev<T, K>(g1, g1p, lane);
+    lrow_prev<T, K, W>(g1, g1p, L);
 #pragma unroll
     for (int q = 0; q < K; q++) {
         const T bhalf = Bk[q] - (dt * T(0.5)) * (g1[q] - g1p[q]);
         qh[q] = vv[q] * bhalf;
     }
     T qhm[K], qhp[K], sq[K], sqp[K];
-    lrow_prev<T, K>(qh, qhm, lane);
-    lrow_next<T, K>(qh, qhp, lane);
+    lrow_prev<T, K, W>(qh, qhm, L);
+    lrow_next<T, K, W>(qh, qhp, L);
 #pragma unroll
     for (int q = 0; q < K; q++) sq[q] = vanleer_half(qh[q] - qhm[q], qhp[q] - qh[q]);
-    lrow_next<T, K>(sq, sqp, lane);
+    lrow_next<T, K, W>(sq, sqp, L);
 #pragma unroll
     for (int q = 0; q < K; q++) G[q] = ev[q] > T(0) ? qh[q] + sq[q] : qhp[q] - sqp[q];
-    lrow_prev<T, K>(G, gm, lane);
+    lrow_prev<T, K, W>(G, gm, L);
 }
 
 // Field update of ct_x_body on a lane row: from rho and m_x of the row (r, m)
 // and the old faces, the new faces nB = (B_x, B_y, B_y(+y), B_z, B_z(+z)).
-template <typename T, int K>
-__device__ __forceinline__ void lrow_field(const T* __restrict__ uin, const T* __restrict__ bin, const LRowSite S,
+template <typename T, int K, int W>
+__device__ __forceinline__ void lrow_field(const T* __restrict__ uin, const T* __restrict__ bin, const LRowSite<W>& S,
                                            T dt, bool frozen, const T (&r)[K], const T (&m)[K], T (&nB)[5][K])
 {
     const long long N = S.N;
-    const int lane = S.lane;
+    const LRowLanes<W>& L = S.L;
     T bx[K], B0[K], B1[K], B2[K], B3[K];
 #pragma unroll
     for (int q = 0; q < K; q++) {
-        const int x = lane + 64 * q;
+        const int x = lrow_x(L, q);
         bx[q] = bin[S.rb + x];
         B0[q] = bin[N + S.rb + x];
         B1[q] = bin[N + S.ryp + x];
@@ -1669,10 +1698,10 @@ __device__ __forceinline__ void lrow_field(const T* __restrict__ uin, const T* _
         B3[q] = bin[2 * N + S.rzp + x];
     }
     T G0[K], g0[K], G1[K], g1[K], G2[K], g2[K], G3[K], g3[K];
-    lrow_emf<T, K, 0>(uin, S, dt, r, m, B0, G0, g0);
-    lrow_emf<T, K, 1>(uin, S, dt, r, m, B1, G1, g1);
-    lrow_emf<T, K, 2>(uin, S, dt, r, m, B2, G2, g2);
-    lrow_emf<T, K, 3>(uin, S, dt, r, m, B3, G3, g3);
+    lrow_emf<T, K, W, 0>(uin, S, dt, r, m, B0, G0, g0);
+    lrow_emf<T, K, W, 1>(uin, S, dt, r, m, B1, G1, g1);
+    lrow_emf<T, K, W, 2>(uin, S, dt, r, m, B2, G2, g2);
+    lrow_emf<T, K, W, 3>(uin, S, dt, r, m, B3, G3, g3);
     // (selects, not branches: a branch here made the compiler address these
     // arrays through a stack copy)
 #pragma unroll
@@ -1691,28 +1720,17 @@ __device__ __forceinline__ void lrow_field(const T* __restrict__ uin, const T* _
 }
 
 // Logical workgroup lb holds rows 4 lb .. 4 lb + 3.
-template <typename T, int K, bool CFL>
+template <typename T, int K, int W, bool CFL>
 __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, T* __restrict__ uout,
                                                      const T* __restrict__ bin, T* __restrict__ bout,
                                                      const Grid& g, T gamma, const Ctl* __restrict__ ctl,
                                                      double dt_arg, unsigned lb,
                                                      unsigned long long* __restrict__ part)
 {
-    const int lane = threadIdx.x & 63;
-    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    const unsigned nrows = (unsigned)ny * (unsigned)nz;
-    const unsigned rw = lb * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const bool live = rw < nrows;         // wavefronts past the last row only join the block reduction
-    const unsigned row = live ? rw : 0u;
-    const int j = (int)(row % (unsigned)ny), k = (int)(row / (unsigned)ny);
-    const int jm = wrap_idx(j - 1, ny, g.bc), jp = wrap_idx(j + 1, ny, g.bc);
-    const int km = wrap_idx(k - 1, nz, g.bc), kp = wrap_idx(k + 1, nz, g.bc);
-    const long long N = g.N;
-    const long long rb = (long long)nx * (j + (long long)ny * k);
-    const long long rym = (long long)nx * (jm + (long long)ny * k);
-    const long long ryp = (long long)nx * (jp + (long long)ny * k);
-    const long long rzm = (long long)nx * (j + (long long)ny * km);
-    const long long rzp = (long long)nx * (j + (long long)ny * kp);
+    const LRowSite<W> S = lrow_site<W>(g, lb);
+    const LRowLanes<W>& L = S.L;
+    const bool live = S.live;   // lanes past the last row only join the block reduction
+    const long long N = S.N, rb = S.rb, rym = S.rym, ryp = S.ryp, rzm = S.rzm, rzp = S.rzp;
     const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
     const bool frozen = ctl->status != 0;
 
@@ -1720,7 +1738,7 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
     T u[5][K], bx[K], nB[5][K], G[4][K], gm[4][K], Bk[4][K];
 #pragma unroll
     for (int q = 0; q < K; q++) {
-        const int x = lane + 64 * q;
+        const int x = lrow_x(L, q);
         const long long c = rb + x;
         u[0][q] = uin[c];
         u[1][q] = uin[N + c];
@@ -1739,44 +1757,44 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
         T vh[K];
 #pragma unroll
         for (int q = 0; q < K; q++) {
-            const int x = lane + 64 * q;
+            const int x = lrow_x(L, q);
             const T r0 = u[0][q], m0 = u[1][q];
             const T rn0 = uin[rn + x], mn0 = uin[N + rn + x];
             // lower neighbour first for pencils 0 and 2, own cell first for 1 and 3
             vh[q] = (e & 1) ? qdiv(m0 + mn0, r0 + rn0) : qdiv(mn0 + m0, rn0 + r0);
         }
         T vn[K], vp[K], vv[K], qb[K];
-        lrow_next<T, K>(vh, vn, lane);
-        lrow_prev<T, K>(vh, vp, lane);
+        lrow_next<T, K, W>(vh, vn, L);
+        lrow_prev<T, K, W>(vh, vp, L);
 #pragma unroll
         for (int q = 0; q < K; q++) {
             vv[q] = T(0.25) * (vp[q] + T(2) * vh[q] + vn[q]);
             qb[q] = vv[q] * Bk[e][q];
         }
         T vvn[K], qbn[K], ev[K], g1[K];
-        lrow_next<T, K>(vv, vvn, lane);
-        lrow_next<T, K>(qb, qbn, lane);
+        lrow_next<T, K, W>(vv, vvn, L);
+        lrow_next<T, K, W>(qb, qbn, L);
 #pragma unroll
         for (int q = 0; q < K; q++) {
             ev[q] = T(0.5) * (vv[q] + vvn[q]);
             g1[q] = ev[q] > T(0) ? qb[q] : qbn[q];
         }
         T g1p[K], qh[K];
-        lrow_prev<T, K>(g1, g1p, lane);
+        lrow_prev<T, K, W>(g1, g1p, L);
 #pragma unroll
         for (int q = 0; q < K; q++) {
             const T bhalf = Bk[e][q] - (dt * T(0.5)) * (g1[q] - g1p[q]);
             qh[q] = vv[q] * bhalf;
         }
         T qhm[K], qhp[K], sq[K], sqp[K];
-        lrow_prev<T, K>(qh, qhm, lane);
-        lrow_next<T, K>(qh, qhp, lane);
+        lrow_prev<T, K, W>(qh, qhm, L);
+        lrow_next<T, K, W>(qh, qhp, L);
 #pragma unroll
         for (int q = 0; q < K; q++) sq[q] = vanleer_half(qh[q] - qhm[q], qhp[q] - qh[q]);
-        lrow_next<T, K>(sq, sqp, lane);
+        lrow_next<T, K, W>(sq, sqp, L);
 #pragma unroll
         for (int q = 0; q < K; q++) G[e][q] = ev[q] > T(0) ? qh[q] + sq[q] : qhp[q] - sqp[q];
-        lrow_prev<T, K>(G[e], gm[e], lane);
+        lrow_prev<T, K, W>(G[e], gm[e], L);
     }
 #pragma unroll
     for (int q = 0; q < K; q++) {
@@ -1794,7 +1812,7 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
             nB[0][q] = (bx[q] + dt * (gm[1][q] - gm[0][q])) + dt * (gm[3][q] - gm[2][q]);
         }
         if (live) {
-            const long long c = rb + lane + 64 * q;
+            const long long c = rb + lrow_x(L, q);
             bout[c] = nB[0][q];
             bout[N + c] = nB[1][q];
             bout[2 * N + c] = nB[3][q];
@@ -1802,7 +1820,7 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
     }
     // ---- fluid update (as in fluid_x_body) on the new field, set by set where no neighbour is needed
     T bxn[K];
-    lrow_next<T, K>(nB[0], bxn, lane);
+    lrow_next<T, K, W>(nB[0], bxn, L);
     T b[3][K], rr[5][K], ll[5][K];
 #pragma unroll
     for (int q = 0; q < K; q++) {
@@ -1823,7 +1841,7 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
 #pragma unroll
     for (int m = 0; m < 5; m++) {
         T lln[K];
-        lrow_next<T, K>(ll[m], lln, lane);
+        lrow_next<T, K, W>(ll[m], lln, L);
 #pragma unroll
         for (int q = 0; q < K; q++) f[m][q] = rr[m][q] - lln[q];
     }
@@ -1833,7 +1851,7 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
 #pragma unroll
         for (int m = 0; m < 5; m++) {
             T fp_[K];
-            lrow_prev<T, K>(f[m], fp_, lane);
+            lrow_prev<T, K, W>(f[m], fp_, L);
 #pragma unroll
             for (int q = 0; q < K; q++) uh[m][q] = u[m][q] - (dt * T(0.5)) * (f[m][q] - fp_[q]);
         }
@@ -1854,25 +1872,25 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
 #pragma unroll
     for (int m = 0; m < 5; m++) {
         T a[K], d[K], al[K], dl[K], Rr[K], Ll[K], Lln[K], fp[K], fm[K];
-        lrow_prev<T, K>(rp[m], a, lane);
-        lrow_next<T, K>(rp[m], d, lane);
-        lrow_prev<T, K>(lp[m], al, lane);
-        lrow_next<T, K>(lp[m], dl, lane);
+        lrow_prev<T, K, W>(rp[m], a, L);
+        lrow_next<T, K, W>(rp[m], d, L);
+        lrow_prev<T, K, W>(lp[m], al, L);
+        lrow_next<T, K, W>(lp[m], dl, L);
 #pragma unroll
         for (int q = 0; q < K; q++) {
             const T c0 = rp[m][q], cl = lp[m][q];
             Rr[q] = c0 + vanleer_half(c0 - a[q], d[q] - c0);
             Ll[q] = cl - vanleer_half(cl - al[q], dl[q] - cl);
         }
-        lrow_next<T, K>(Ll, Lln, lane);
+        lrow_next<T, K, W>(Ll, Lln, L);
 #pragma unroll
         for (int q = 0; q < K; q++) fp[q] = Rr[q] - Lln[q];
-        lrow_prev<T, K>(fp, fm, lane);
+        lrow_prev<T, K, W>(fp, fm, L);
 #pragma unroll
         for (int q = 0; q < K; q++) {
             // the new state overwrites u (its old value is not needed any more)
             u[m][q] = frozen ? u[m][q] : u[m][q] - dt * (fp[q] - fm[q]);
-            if (live) uout[m * N + rb + lane + 64 * q] = u[m][q];
+            if (live) uout[m * N + rb + lrow_x(L, q)] = u[m][q];
         }
     }
     if constexpr (CFL) {
@@ -1886,38 +1904,39 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
     }
 }
 
-template <typename T, int K, bool CFL>
+template <typename T, int K, int W, bool CFL>
 __global__ void __launch_bounds__(256) ct_fluid_x_lrow(const T* __restrict__ uin, T* __restrict__ uout,
                                                        const T* __restrict__ bin, T* __restrict__ bout, Grid g,
                                                        T gamma, const Ctl* __restrict__ ctl, double dt_arg,
                                                        unsigned long long* __restrict__ parts, int* count)
 {
     if constexpr (CFL) store_part_count(count);
-    ct_fluid_x_lrow_body<T, K, CFL>(uin, uout, bin, bout, g, gamma, ctl, dt_arg, blockIdx.x, parts + blockIdx.x);
+    ct_fluid_x_lrow_body<T, K, W, CFL>(uin, uout, bin, bout, g, gamma, ctl, dt_arg, blockIdx.x,
+                                       parts + blockIdx.x);
 }
 
 // B_{y->x}, B_{z->x} alone on a lane row (as ct_x_body); logical workgroup
 // lb holds rows 4 lb .. 4 lb + 3.
-template <typename T, int K>
+template <typename T, int K, int W>
 __device__ __forceinline__ void ct_x_lrow_body(const T* __restrict__ uf, const T* __restrict__ bin,
                                                T* __restrict__ bout, const Grid& g, const Ctl* __restrict__ ctl,
                                                double dt_arg, unsigned lb)
 {
-    const LRowSite S = lrow_site(g, lb);
+    const LRowSite<W> S = lrow_site<W>(g, lb);
     const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
     const bool frozen = ctl->status != 0;
     T r[K], m[K], nB[5][K];
 #pragma unroll
     for (int q = 0; q < K; q++) {
-        const long long c = S.rb + S.lane + 64 * q;
+        const long long c = S.rb + lrow_x(S.L, q);
         r[q] = uf[c];
         m[q] = uf[S.N + c];
     }
-    lrow_field<T, K>(uf, bin, S, dt, frozen, r, m, nB);
+    lrow_field<T, K, W>(uf, bin, S, dt, frozen, r, m, nB);
     if (S.live) {
 #pragma unroll
         for (int q = 0; q < K; q++) {
-            const long long c = S.rb + S.lane + 64 * q;
+            const long long c = S.rb + lrow_x(S.L, q);
             bout[c] = nB[0][q];
             bout[S.N + c] = nB[1][q];
             bout[2 * S.N + c] = nB[3][q];
@@ -1925,33 +1944,33 @@ __device__ __forceinline__ void ct_x_lrow_body(const T* __restrict__ uf, const T
     }
 }
 
-template <typename T, int K>
+template <typename T, int K, int W>
 __global__ void __launch_bounds__(256) ct_x_lrow(const T* __restrict__ uf, const T* __restrict__ bin,
                                                  T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
                                                  double dt_arg)
 {
-    ct_x_lrow_body<T, K>(uf, bin, bout, g, ctl, dt_arg, blockIdx.x);
+    ct_x_lrow_body<T, K, W>(uf, bin, bout, g, ctl, dt_arg, blockIdx.x);
 }
 
 // fluid_x alone on a lane row (as fluid_x_body); batches use it on rows of 64
 // and 128 cells, where the wavefront form wastes a third to a half of its
 // lanes.
 // With CFL the rows' largest CFL speed goes to part (all threads take part).
-template <typename T, int K, bool CFL>
+template <typename T, int K, int W, bool CFL>
 __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* __restrict__ uout,
                                                   const T* __restrict__ bf, const Grid& g, T gamma,
                                                   const Ctl* __restrict__ ctl, double dt_arg, unsigned lb,
                                                   unsigned long long* __restrict__ part)
 {
-    const LRowSite S = lrow_site(g, lb);
+    const LRowSite<W> S = lrow_site<W>(g, lb);
     const long long N = S.N;
-    const int lane = S.lane;
+    const LRowLanes<W>& L = S.L;
     const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
     const bool frozen = ctl->status != 0;
     T u[5][K], b[3][K], bx[K], bxn[K];
 #pragma unroll
     for (int q = 0; q < K; q++) {
-        const int x = lane + 64 * q;
+        const int x = lrow_x(L, q);
         const long long c = S.rb + x;
 #pragma unroll
         for (int m = 0; m < 5; m++) u[m][q] = uin[m * N + c];
@@ -1959,7 +1978,7 @@ __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* 
         b[1][q] = T(0.5) * (bf[N + c] + bf[N + S.ryp + x]);
         b[2][q] = T(0.5) * (bf[2 * N + c] + bf[2 * N + S.rzp + x]);
     }
-    lrow_next<T, K>(bx, bxn, lane);
+    lrow_next<T, K, W>(bx, bxn, L);
 #pragma unroll
     for (int q = 0; q < K; q++) b[0][q] = T(0.5) * (bx[q] + bxn[q]);
     T rr[5][K], ll[5][K];
@@ -1979,7 +1998,7 @@ __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* 
 #pragma unroll
     for (int m = 0; m < 5; m++) {
         T lln[K];
-        lrow_next<T, K>(ll[m], lln, lane);
+        lrow_next<T, K, W>(ll[m], lln, L);
 #pragma unroll
         for (int q = 0; q < K; q++) f[m][q] = rr[m][q] - lln[q];
     }
@@ -1989,7 +2008,7 @@ __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* 
 #pragma unroll
         for (int m = 0; m < 5; m++) {
             T fp_[K];
-            lrow_prev<T, K>(f[m], fp_, lane);
+            lrow_prev<T, K, W>(f[m], fp_, L);
 #pragma unroll
             for (int q = 0; q < K; q++) uh[m][q] = u[m][q] - (dt * T(0.5)) * (f[m][q] - fp_[q]);
         }
@@ -2009,24 +2028,24 @@ __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* 
 #pragma unroll
     for (int m = 0; m < 5; m++) {
         T a[K], d[K], al[K], dl[K], Rr[K], Ll[K], Lln[K], fp[K], fm[K];
-        lrow_prev<T, K>(rp[m], a, lane);
-        lrow_next<T, K>(rp[m], d, lane);
-        lrow_prev<T, K>(lp[m], al, lane);
-        lrow_next<T, K>(lp[m], dl, lane);
+        lrow_prev<T, K, W>(rp[m], a, L);
+        lrow_next<T, K, W>(rp[m], d, L);
+        lrow_prev<T, K, W>(lp[m], al, L);
+        lrow_next<T, K, W>(lp[m], dl, L);
 #pragma unroll
         for (int q = 0; q < K; q++) {
             const T c0 = rp[m][q], cl = lp[m][q];
             Rr[q] = c0 + vanleer_half(c0 - a[q], d[q] - c0);
             Ll[q] = cl - vanleer_half(cl - al[q], dl[q] - cl);
         }
-        lrow_next<T, K>(Ll, Lln, lane);
+        lrow_next<T, K, W>(Ll, Lln, L);
 #pragma unroll
         for (int q = 0; q < K; q++) fp[q] = Rr[q] - Lln[q];
-        lrow_prev<T, K>(fp, fm, lane);
+        lrow_prev<T, K, W>(fp, fm, L);
 #pragma unroll
         for (int q = 0; q < K; q++) {
             u[m][q] = frozen ? u[m][q] : u[m][q] - dt * (fp[q] - fm[q]);
-            if (S.live) uout[m * N + S.rb + lane + 64 * q] = u[m][q];
+            if (S.live) uout[m * N + S.rb + lrow_x(L, q)] = u[m][q];
         }
     }
     if constexpr (CFL) {
@@ -2041,36 +2060,71 @@ __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* 
     }
 }
 
-template <typename T, int K, bool CFL>
+template <typename T, int K, int W, bool CFL>
 __global__ void __launch_bounds__(256) fluid_x_lrow(const T* __restrict__ uin, T* __restrict__ uout,
                                                     const T* __restrict__ bf, Grid g, T gamma,
                                                     const Ctl* __restrict__ ctl, double dt_arg,
                                                     unsigned long long* __restrict__ parts, int* count)
 {
     if constexpr (CFL) store_part_count(count);
-    fluid_x_lrow_body<T, K, CFL>(uin, uout, bf, g, gamma, ctl, dt_arg, blockIdx.x, parts + blockIdx.x);
+    fluid_x_lrow_body<T, K, W, CFL>(uin, uout, bf, g, gamma, ctl, dt_arg, blockIdx.x, parts + blockIdx.x);
 }
 
-// Cells per lane of the lane-row form on periodic rows of 64, 128, 192 or 256
-// cells (0: not applicable). The field update along x takes it in both
-// precisions (FP64 256^3: 0.303 -> 0.254 ms against the wavefront form); the
-// fluid update and the fused reverse L_x take it in FP32 only: in FP64 the
-// fluid update measured 0.379 ms against 0.357 for the wavefront form, and
-// the fused sweep needs 247-256 VGPRs in this form and runs in the
-// row-per-workgroup form instead.
-static int x_lrow_k(const Grid& g)
+// Shape of the lane-row form on a periodic grid: W lanes per row and K cells
+// per lane, rows of W K cells (returns K, 0 where the form does not apply):
+// rows of 64, 128, 192 or 256 cells fill a wavefront each (W = 64, K = 1-4);
+// rows of 32 and 96 cells share one two at a time (W = 32, K = 1 or 3), rows
+// of 48 four at a time (W = 16, K = 3). Rows of other lengths run the
+// wavefront form. The field update along x takes the form in both precisions
+// (FP64 256^3: 0.303 -> 0.254 ms against the wavefront form); the fluid update
+// and the fused reverse L_x take it in FP32 only: in FP64 the fluid update
+// measured 0.379 ms against 0.357 for the wavefront form, and the fused sweep
+// needs 247-256 VGPRs in this form and runs in the row-per-workgroup form
+// instead.
+static int x_lrow_k(const Grid& g, int* W, int kmax = 4)
 {
-    if (g.bc != 0 || g.n[0] % 64 != 0 || g.n[0] > 256) return 0;
-    return g.n[0] / 64;
+    if (g.bc != 0) return 0;
+    const int n = g.n[0];
+    int w = 0, k = 0;
+    if (n % 64 == 0 && n <= 256) {
+        w = 64;
+        k = n / 64;
+    } else if (n == 32 || n == 96) {
+        w = 32;
+        k = n / 32;
+    } else if (n == 48) {
+        w = 16;
+        k = 3;
+    }
+    if (k == 0 || k > kmax) return 0;
+    *W = w;
+    return k;
 }
+
+// Calls X(K, W) for the (K, W) of the grid's lane-row shape.
+#define MHD_LROW_DISPATCH(K, W, X)                 \
+    switch ((K) * 100 + (W)) {                     \
+    case 164: X(1, 64) break;                      \
+    case 264: X(2, 64) break;                      \
+    case 364: X(3, 64) break;                      \
+    case 464: X(4, 64) break;                      \
+    case 132: X(1, 32) break;                      \
+    case 332: X(3, 32) break;                      \
+    default: X(3, 16) break;                       \
+    }
 
 template <typename T>
-static int x_lrow_k_fluid(const Grid& g)
+static int x_lrow_k_fluid(const Grid& g, int* W)
 {
-    return kExact<T> ? 0 : x_lrow_k(g);
+    return kExact<T> ? 0 : x_lrow_k(g, W);
 }
 
-static unsigned x_lrow_blocks(const Grid& g) { return (unsigned)(((long long)g.n[1] * g.n[2] + 3) / 4); }
+// Workgroups of a lane-row launch: four wavefronts of 64 / W rows each.
+static unsigned x_lrow_blocks(const Grid& g, int W)
+{
+    const long long rows_per_block = 4LL * (64 / W);
+    return (unsigned)(((long long)g.n[1] * g.n[2] + rows_per_block - 1) / rows_per_block);
+}
 
 // ---------------------------------------------------------------------------
 constexpr int RB = 256;   // threads per block of the reductions
@@ -2210,26 +2264,15 @@ static void fluid_launch(int axis, const T* u_in, T* u_out, const T* b, Grid g, 
                          double dt, unsigned long long* parts, hipStream_t s)
 {
     int* count = CFL ? &ctl->nparts : nullptr;
-    if (axis == 0 && x_lrow_k_fluid<T>(g)) {
-        const unsigned nb = x_lrow_blocks(g);
-        switch (x_lrow_k_fluid<T>(g)) {
-        case 1:
-            hipLaunchKernelGGL((fluid_x_lrow<T, 1, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl,
-                               dt, parts, count);
-            break;
-        case 2:
-            hipLaunchKernelGGL((fluid_x_lrow<T, 2, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl,
-                               dt, parts, count);
-            break;
-        case 3:
-            hipLaunchKernelGGL((fluid_x_lrow<T, 3, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl,
-                               dt, parts, count);
-            break;
-        default:
-            hipLaunchKernelGGL((fluid_x_lrow<T, 4, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl,
-                               dt, parts, count);
-            break;
-        }
+    int W = 64;
+    const int K = axis == 0 ? x_lrow_k_fluid<T>(g, &W) : 0;
+    if (K) {
+        const unsigned nb = x_lrow_blocks(g, W);
+#define MHD_LROW_FLUID(KK, WW)                                                                                \
+    hipLaunchKernelGGL((fluid_x_lrow<T, KK, WW, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl, \
+                       dt, parts, count);
+        MHD_LROW_DISPATCH(K, W, MHD_LROW_FLUID)
+#undef MHD_LROW_FLUID
     } else if (axis == 0) {
         const unsigned nb = x_wave_blocks(g);
         hipLaunchKernelGGL((fluid_x_wave<T, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
@@ -2288,23 +2331,19 @@ hipError_t launch_ct_fluid(int axis, const T* u_in, T* u_out, const T* b_in, T* 
                            Ctl* ctl, double dt, unsigned long long* parts, hipStream_t s)
 {
     if (axis < 0 || axis > 2 || g.bc != 0) return hipErrorInvalidValue;
-    if (axis == 0 && x_lrow_k_fluid<T>(g)) {
-        const unsigned nb = x_lrow_blocks(g);
-        const int K = x_lrow_k_fluid<T>(g);
-#define MHD_LROW_LAUNCH(KK)                                                                                    \
-    if (K == KK) {                                                                                            \
-        if (parts)                                                                                            \
-            hipLaunchKernelGGL((ct_fluid_x_lrow<T, KK, true>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in,   \
-                               b_out, g, (T)gamma, ctl, dt, parts, &ctl->nparts);                            \
-        else                                                                                                  \
-            hipLaunchKernelGGL((ct_fluid_x_lrow<T, KK, false>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in,  \
-                               b_out, g, (T)gamma, ctl, dt, nullptr, nullptr);                               \
-    }
-        MHD_LROW_LAUNCH(1)
-        MHD_LROW_LAUNCH(2)
-        MHD_LROW_LAUNCH(3)
-        MHD_LROW_LAUNCH(4)
-#undef MHD_LROW_LAUNCH
+    int W = 64;
+    const int K = axis == 0 ? x_lrow_k_fluid<T>(g, &W) : 0;
+    if (K) {
+        const unsigned nb = x_lrow_blocks(g, W);
+#define MHD_LROW_FUSED(KK, WW)                                                                                \
+    if (parts)                                                                                                \
+        hipLaunchKernelGGL((ct_fluid_x_lrow<T, KK, WW, true>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in, b_out, \
+                           g, (T)gamma, ctl, dt, parts, &ctl->nparts);                                        \
+    else                                                                                                      \
+        hipLaunchKernelGGL((ct_fluid_x_lrow<T, KK, WW, false>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in,      \
+                           b_out, g, (T)gamma, ctl, dt, nullptr, nullptr);
+        MHD_LROW_DISPATCH(K, W, MHD_LROW_FUSED)
+#undef MHD_LROW_FUSED
         return hipGetLastError();
     }
     if (axis == 0 && ct_fluid_x_row_ok<T>(g)) {
@@ -2352,14 +2391,14 @@ template <typename T>
 hipError_t launch_ct(int axis, const T* u, const T* b_in, T* b_out, Grid g, const Ctl* ctl, double dt,
                      hipStream_t s)
 {
-    if (axis == 0 && x_lrow_k(g)) {
-        const unsigned nb = x_lrow_blocks(g);
-        switch (x_lrow_k(g)) {
-        case 1: hipLaunchKernelGGL((ct_x_lrow<T, 1>), dim3(nb), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt); break;
-        case 2: hipLaunchKernelGGL((ct_x_lrow<T, 2>), dim3(nb), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt); break;
-        case 3: hipLaunchKernelGGL((ct_x_lrow<T, 3>), dim3(nb), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt); break;
-        default: hipLaunchKernelGGL((ct_x_lrow<T, 4>), dim3(nb), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt); break;
-        }
+    int W = 64;
+    const int K = axis == 0 ? x_lrow_k(g, &W) : 0;
+    if (K) {
+        const unsigned nb = x_lrow_blocks(g, W);
+#define MHD_LROW_CT(KK, WW) \
+    hipLaunchKernelGGL((ct_x_lrow<T, KK, WW>), dim3(nb), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt);
+        MHD_LROW_DISPATCH(K, W, MHD_LROW_CT)
+#undef MHD_LROW_CT
     } else if (axis == 0) {
         hipLaunchKernelGGL((ct_x_wave<T>), dim3(ct_x_wave_blocks(g)), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt);
     } else {

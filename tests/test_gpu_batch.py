@@ -177,9 +177,11 @@ def test_batch_autotune_keeps_results(B, dtype):
             for kind in range(1, B.MHD_K_CTFLUID_Z + 1):
                 p0, p1 = B.mhd_batch_tile(bt.b, pid, kind)
                 if kind in (B.MHD_K_FLUID_X, B.MHD_K_CT_X, B.MHD_K_CTFLUID_X):
-                    # wavefront form, or the lane-row form on FP32 periodic rows of 64 or 128 cells
-                    lrow = dtype == B.MHD_F32 and bc == 0 and nx in (64, 128)
-                    assert p1 == 0 and p0 in ((0, nx // 64) if lrow else (0,))
+                    # wavefront form (0, 0), or on FP32 periodic rows the lane-row form
+                    # (K cells per lane, W lanes per row) where the row length has one
+                    shape = {64: (1, 64), 128: (2, 64), 32: (1, 32), 96: (3, 32), 48: (3, 16)}.get(nx)
+                    lrow = dtype == B.MHD_F32 and bc == 0 and shape is not None
+                    assert (p0, p1) in ((0, 0), shape) if lrow else (p0, p1) == (0, 0)
                 else:
                     axis = 1 if kind in (B.MHD_K_FLUID_Y, B.MHD_K_CT_Y, B.MHD_K_CTFLUID_Y) else 2
                     assert p0 <= s.shape[3 - axis]
@@ -304,15 +306,16 @@ def test_flat_axes_match_the_marching_field_sweep(B, dtype):
             assert bt.time(pid) == tw
 
 
-@pytest.mark.parametrize("nx", [64, 128, 192, 256])
+@pytest.mark.parametrize("nx", [32, 48, 64, 96, 128, 192, 256])
 def test_lane_row_x_sweeps_equal_batched_wavefront_form(B, nx):
-    """A plain FP32 handle on periodic rows of 64 k cells runs the x sweeps in
-    the lane-row form (a whole row per wavefront) and the reverse L_x fused; a
-    batch whose x sweeps (the fused reverse one included) are pinned to the
-    wavefront form (the autotuner's other candidate) runs the wavefront-form
-    bodies. Both must give the same bits, with fusion on and off, after steps
-    in all three sweep orders; so must the batch with its default tiles (the
-    lane-row form on rows of 64 and 128 cells)."""
+    """A plain FP32 handle on periodic rows of 64 k cells (a whole row per
+    wavefront) or of 32, 48 and 96 cells (two or four rows per wavefront) runs
+    the x sweeps in the lane-row form and the reverse L_x fused; a batch whose
+    x sweeps (the fused reverse one included) are pinned to the wavefront form
+    (the autotuner's other candidate) runs the wavefront-form bodies. Both
+    must give the same bits, with fusion on and off, after steps in all three
+    sweep orders; so must the batch with its default tiles (the lane-row form
+    on rows of 32, 48, 64, 96 and 128 cells)."""
     ny, nz = 11, 6
     s = P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 340 + nx)
     note("lane-row x sweeps, %d x %d x %d fp32" % (nx, ny, nz))

@@ -61,8 +61,12 @@ SUBOP_CASES = [
     ((5, 130, 3), 0),
     ((3, 4, 131), 1),
     ((600, 3, 2), 0),
-    # periodic rows of 64 k cells: the x sweeps take their row forms
+    # periodic rows of 64 k cells: the x sweeps take their row forms; rows of
+    # 96, 48 and 32 cells share a wavefront in the lane-row field update
     ((128, 9, 7), 0),
+    ((96, 7, 5), 0),
+    ((48, 9, 4), 0),
+    ((32, 5, 6), 0),
 ]
 
 
