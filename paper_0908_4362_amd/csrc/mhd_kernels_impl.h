@@ -442,11 +442,33 @@ __host__ __device__ inline int march_wx(int axis, int nx, int nt, bool xwide)
 template <typename T, bool CT>
 constexpr bool kMarchXWide = !(CT && kExact<T>);
 
+// Rows that are not a multiple of 64 cells would leave lanes of their last
+// wavefront idle (a 96-cell row keeps 96 of 128 lanes busy, a 32-cell row
+// half): there the lanes of a marching launch take consecutive positions of
+// the flattened (x, TA) plane instead, x fastest and running on into the next
+// transverse row (packed layout), so every lane but those past the plane's
+// end has a pencil. A pencil's arithmetic does not depend on which lane runs
+// it, so the layout never changes a result.
+__host__ __device__ inline bool march_packed(int nx) { return nx % 64 != 0; }
+
 template <int D, bool XWIDE>
 __device__ __forceinline__ MarchTile march_tile(const Grid& g, int chunk, unsigned lb)
 {
     constexpr int TA = (D == 1) ? 2 : 1;
     const int nx = g.n[0], nd = g.n[D], nt = g.n[TA];
+    if (march_packed(nx)) {
+        const long long P = (long long)nx * nt;
+        const unsigned ntp = (unsigned)((P + 64 * MW - 1) / (64 * MW));
+        const unsigned pt = lb % ntp, ch = lb / ntp;
+        const long long c = (long long)pt * (64 * MW) + threadIdx.y * 64 + threadIdx.x;
+        MarchTile m;
+        m.i = (int)(c % nx);
+        m.tc = (int)(c / nx);
+        m.o0 = ch * chunk;
+        m.o1 = min(m.o0 + chunk, nd);
+        m.active = c < P && m.o0 < m.o1;
+        return m;
+    }
     const unsigned wx = (unsigned)march_wx(D, nx, nt, XWIDE), wt = MW / wx;
     const unsigned ntx = (nx + 64 * wx - 1) / (64 * wx), ntg = (nt + wt - 1) / wt;
     const unsigned xt = lb % ntx, rest = lb / ntx;
@@ -2219,7 +2241,8 @@ int reduce_blocks(const Grid& g)
 int march_chunk(const Grid& g, int d, int ghost, long long target, bool fill = false)
 {
     const int ta = (d == 1) ? 2 : 1;
-    const long long waves = ((g.n[0] + 63) / 64) * (long long)g.n[ta];
+    const long long waves = march_packed(g.n[0]) ? ((long long)g.n[0] * g.n[ta] + 63) / 64
+                                                 : ((g.n[0] + 63) / 64) * (long long)g.n[ta];
     const int nd = g.n[d];
     long long want = target / (waves > 0 ? waves : 1);
     if (want < 1) want = 1;
@@ -2236,6 +2259,10 @@ int march_chunk(const Grid& g, int d, int ghost, long long target, bool fill = f
 static unsigned march_blocks(const Grid& g, int axis, int chunk, bool xwide)
 {
     const int ta = (axis == 1) ? 2 : 1;
+    if (march_packed(g.n[0])) {
+        const long long P = (long long)g.n[0] * g.n[ta];
+        return (unsigned)(((P + 64 * MW - 1) / (64 * MW)) * ((g.n[axis] + chunk - 1) / chunk));
+    }
     const int wx = march_wx(axis, g.n[0], g.n[ta], xwide), wt = MW / wx;
     return (unsigned)(((g.n[0] + 64 * wx - 1) / (64 * wx)) * ((g.n[ta] + wt - 1) / wt) *
                       ((g.n[axis] + chunk - 1) / chunk));
