@@ -45,6 +45,17 @@ WORDS_PER_CELL = {"cfl": 8, "fluid_x": 13, "fluid_y": 13, "fluid_z": 13, "ct_x":
 STEP_WORDS = 104  # minimum per full step: 6 directional operators x (8 read + 8 written) + 8 for the CFL
 
 
+def repeat_summary(reps, steps):
+    """Per-step times of the repeated K-step passes (after the headline pass) and their median."""
+    if not reps:
+        return None
+    ms = sorted(r * 1e3 / steps for r in reps)
+    mid = len(ms) // 2
+    med = ms[mid] if len(ms) % 2 else 0.5 * (ms[mid - 1] + ms[mid])
+    return {"passes": len(ms), "steps_each": steps, "median_ms_per_step": round(med, 4),
+            "min_ms_per_step": round(ms[0], 4), "max_ms_per_step": round(ms[-1], 4)}
+
+
 def design_step_words(kern, steps):
     """Words per cell per full step of the launches the step ran (the instrumented pass's launch
     counts times each kind's words; the c_max reduction rides on the last fluid launch of the previous
@@ -67,10 +78,11 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def run_gpu(B, P, n, dtype, warmup, steps, stream):
+def run_gpu(B, P, n, dtype, warmup, steps, stream, repeats=5):
     """W warm-up steps; then the headline pass, K full steps timed by the host clock between device
-    synchronisations; then the instrumented pass, K more full steps with a HIP event pair around every
-    launch (mhd_timing), whose per-kernel averages feed the roofline."""
+    synchronisations; then `repeats` more passes of K full steps timed the same way (their median is
+    reported beside the headline); then the instrumented pass, K more full steps with a HIP event pair
+    around every launch (mhd_timing), whose per-kernel averages feed the roofline."""
     nx = ny = nz = n
     sv = B.Solver(nx, ny, nz, 5.0 / 3.0, B.MHD_BC_PERIODIC, dtype)
     B.mhd_set_stream(sv.h, stream)
@@ -84,6 +96,12 @@ def run_gpu(B, P, n, dtype, warmup, steps, stream):
     sv.step(steps, 0.7)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    reps = []
+    for _ in range(repeats):
+        ta = time.perf_counter()
+        sv.step(steps, 0.7)
+        torch.cuda.synchronize()
+        reps.append(time.perf_counter() - ta)
     B.mhd_timing(sv.h, True)
     t2 = time.perf_counter()
     sv.step(steps, 0.7)
@@ -97,7 +115,7 @@ def run_gpu(B, P, n, dtype, warmup, steps, stream):
     divb = sv.divb_max()
     t_sim, s_done = sv.time()
     sv.close()
-    return (t1 - t0), kern, divb, t_sim, s_done, (t3 - t2)
+    return (t1 - t0), kern, divb, t_sim, s_done, (t3 - t2), reps
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -558,6 +576,8 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="further passes of K timed steps after the headline pass; their median is reported")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256, help="cells per axis (workload: 256)")
     ap.add_argument("--cpu-sample", type=int, default=96, help="edge of the box timed on the CPU oracle")
@@ -615,7 +635,8 @@ def main():
         del src, dst
     print("bench: %d^3 blast, fp64, %d warm-up + %d timed steps" % (n, args.warmup, args.steps), file=sys.stderr,
           flush=True)
-    sec64, kern64, divb64, tsim, sdone, inst64 = run_gpu(B, P, n, B.MHD_F64, args.warmup, args.steps, stream)
+    sec64, kern64, divb64, tsim, sdone, inst64, reps64 = run_gpu(B, P, n, B.MHD_F64, args.warmup, args.steps,
+                                                                 stream, args.repeats)
     dom, roof = roofline(kern64, ncell, 8, n)
     out = {
         "metric": "cell-updates/s per full step",
@@ -639,11 +660,13 @@ def main():
                        "cfl_fused_into_last_sweep": True},
         "kernels_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in kern64.items()},
         "instrumented_ms_per_step": round(inst64 * 1e3 / args.steps, 4),
+        "repeats": repeat_summary(reps64, args.steps),
         "divb_max_after": divb64,
     }
     if not args.no_fp32:
         print("bench: %d^3 blast, fp32" % n, file=sys.stderr, flush=True)
-        sec32, kern32, divb32, _, _, inst32 = run_gpu(B, P, n, B.MHD_F32, args.warmup, args.steps, stream)
+        sec32, kern32, divb32, _, _, inst32, reps32 = run_gpu(B, P, n, B.MHD_F32, args.warmup, args.steps,
+                                                              stream, args.repeats)
         _, roof32 = roofline(kern32, ncell, 4, n)
         out["fp32"] = {
             "value": round(ncell * args.steps / sec32, 1),
@@ -653,6 +676,7 @@ def main():
             "step_roofline": step_roofline(sec32 / args.steps, ncell, 4),
             "kernels_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in kern32.items()},
             "instrumented_ms_per_step": round(inst32 * 1e3 / args.steps, 4),
+            "repeats": repeat_summary(reps32, args.steps),
         }
     if not args.no_paper_configs:
         print("bench: the paper's timing workloads", file=sys.stderr, flush=True)

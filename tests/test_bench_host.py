@@ -1,5 +1,6 @@
 """CPU checks of bench.py's host logic: the one-GPU guard, the roofline of
-the dominant kernel, and the traffic table's tie to the kernel source."""
+the dominant kernel, the traffic table's tie to the kernel source, and the
+median of the repeated timing passes."""
 from __future__ import annotations
 
 import os
@@ -50,3 +51,12 @@ def test_traffic_is_reported_only_for_the_profiled_source(tmp_path, monkeypatch)
     src.write_bytes(b"// another kernel source\n")
     monkeypatch.setattr(bench, "KERNEL_SOURCES", (str(src),) + tuple(bench.KERNEL_SOURCES[1:]))
     assert bench.measured_traffic("f64", "fluid_y", 256) is None
+
+
+def test_repeat_summary_reports_the_median_pass():
+    s = bench.repeat_summary([0.071, 0.070, 0.090, 0.069, 0.072], 20)
+    assert s["passes"] == 5 and s["steps_each"] == 20
+    assert s["median_ms_per_step"] == 3.55   # 0.071 s over 20 steps
+    assert s["min_ms_per_step"] == 3.45 and s["max_ms_per_step"] == 4.5
+    assert bench.repeat_summary([0.07, 0.08], 10)["median_ms_per_step"] == 7.5
+    assert bench.repeat_summary([], 20) is None
