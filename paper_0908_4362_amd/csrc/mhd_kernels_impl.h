@@ -1550,6 +1550,100 @@ static bool ct_fluid_x_row_ok(const Grid& g)
     return kExact<T> && g.bc == 0 && g.n[0] % 64 == 0 && g.n[0] <= 64 * XRW;
 }
 
+// fluid_x alone in the row form (FP64 periodic rows of 64 k cells, k <= XRW):
+// one workgroup per row, one cell per lane, neighbours across the
+// wavefront ends exchanged through LDS (six exchanges); the same expressions
+// as fluid_x_body, so the same bits. The wavefront form spends 320 lanes on
+// a 256-cell row (5 wavefronts of 58 stored cells).
+template <typename T, bool CFL>
+__global__ void __launch_bounds__(64 * XRW) fluid_x_row(const T* __restrict__ uin, T* __restrict__ uout,
+                                                        const T* __restrict__ bf, Grid g, T gamma,
+                                                        const Ctl* __restrict__ ctl, double dt_arg,
+                                                        unsigned long long* __restrict__ parts, int* count)
+{
+    __shared__ T xb[2][2][XRW][XRV];
+    __shared__ unsigned long long wmax[XRW];
+    if constexpr (CFL) store_part_count(count);
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int W = blockDim.x >> 6;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const unsigned row = blockIdx.x;
+    const int j = (int)(row % (unsigned)ny), k = (int)(row / (unsigned)ny);
+    const int x = 64 * w + lane;
+    const int jp = wrap_idx(j + 1, ny, g.bc), kp = wrap_idx(k + 1, nz, g.bc);
+    const long long N = g.N;
+    const long long c = (long long)nx * (j + (long long)ny * k) + x;
+    const long long cyp = (long long)nx * (jp + (long long)ny * k) + x;
+    const long long czp = (long long)nx * (j + (long long)ny * kp) + x;
+    const T dt = (T)(dt_arg >= 0.0 ? dt_arg : ctl->dt);
+    const bool frozen = ctl->status != 0;
+    constexpr bool kDpp = kExact<T>;
+    RowX<T> X{xb, 0, w, W, lane};
+
+    T u[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) u[q] = uin[q * N + c];
+    const T bx = bf[c];
+    T b[3];
+    b[1] = T(0.5) * (bf[N + c] + bf[N + cyp]);
+    b[2] = T(0.5) * (bf[2 * N + c] + bf[2 * N + czp]);
+    T bxn;
+    X.template shift<1, true, false, kDpp>(&bx, &bxn, nullptr);
+    b[0] = T(0.5) * (bx + bxn);
+    T rr[5], ll[5];
+    movers(u, b, gamma, rr, ll);
+    T lln[5];
+    X.template shift<5, true, false, kDpp>(ll, lln, nullptr);
+    T f[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) f[q] = rr[q] - lln[q];
+    T fpv[5];
+    X.template shift<5, false, true, kDpp>(f, nullptr, fpv);
+    T uh[5], rp[5], lp[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) uh[q] = u[q] - (dt * T(0.5)) * (f[q] - fpv[q]);
+    movers(uh, b, gamma, rp, lp);
+    T t10[10], t10n[10], t10p[10];
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+        t10[q] = rp[q];
+        t10[5 + q] = lp[q];
+    }
+    X.template shift<10, true, true, kDpp>(t10, t10n, t10p);
+    T Rr[5], Ll[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+        const T a = t10p[q], c0 = rp[q], d = t10n[q];
+        Rr[q] = c0 + vanleer_half(c0 - a, d - c0);
+        const T al = t10p[5 + q], cl = lp[q], dl = t10n[5 + q];
+        Ll[q] = cl - vanleer_half(cl - al, dl - cl);
+    }
+    T Lln[5];
+    X.template shift<5, true, false, kDpp>(Ll, Lln, nullptr);
+    T fp[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) fp[q] = Rr[q] - Lln[q];
+    T fm[5];
+    X.template shift<5, false, true, kDpp>(fp, nullptr, fm);
+    T un[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) un[q] = frozen ? u[q] : u[q] - dt * (fp[q] - fm[q]);
+#pragma unroll
+    for (int q = 0; q < 5; q++) uout[q * N + c] = un[q];
+    if constexpr (CFL) {
+        const T cc = cfl_speed(un[0], un[1], un[2], un[3], un[4], b[0], b[1], b[2], gamma);
+        unsigned long long best = wave_max_u64(speed_bits(cc));
+        if (lane == 0) wmax[w] = best;
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            best = (int)threadIdx.x < W ? wmax[threadIdx.x] : 0ull;
+            best = wave_max_u64(best);
+            if (threadIdx.x == 0) parts[blockIdx.x] = best;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // x sweeps on periodic rows of 64 K cells in FP32, lane-row form: one
 // wavefront holds a whole row, K cells per lane (cell x = lane + 64 s in set
@@ -2300,6 +2394,9 @@ static void fluid_launch(int axis, const T* u_in, T* u_out, const T* b, Grid g, 
                        dt, parts, count);
         MHD_LROW_DISPATCH(K, W, MHD_LROW_FLUID)
 #undef MHD_LROW_FLUID
+    } else if (axis == 0 && ct_fluid_x_row_ok<T>(g)) {
+        hipLaunchKernelGGL((fluid_x_row<T, CFL>), dim3((unsigned)((long long)g.n[1] * g.n[2])),
+                           dim3(64 * (g.n[0] / 64)), 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt, parts, count);
     } else if (axis == 0) {
         const unsigned nb = x_wave_blocks(g);
         hipLaunchKernelGGL((fluid_x_wave<T, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
