@@ -14,9 +14,12 @@
 // Sweeps along y and z march through each pencil: a thread owns one x column
 // (64 consecutive x per wavefront, so every load and store is coalesced) and
 // walks along the sweep axis keeping the stencil window in registers; a pencil
-// is cut into chunks that re-run a short warm-up. Sweeps along x hold 64
-// consecutive cells of a row in the lanes of one wavefront, one cell per lane,
-// and exchange stencil neighbours with cross-lane shuffles.
+// is cut into chunks that re-run a short warm-up. Sweeps along x hold the
+// cells of a row in the lanes of a wavefront and exchange stencil neighbours
+// with cross-lane shuffles: a whole periodic row per wavefront (lane-row form,
+// K cells per lane), a whole row per workgroup (row form, one cell per lane,
+// wavefront ends exchanged through LDS), or 64-cell segments with halo lanes
+// (wavefront form).
 #pragma once
 #include <algorithm>
 #include <type_traits>
@@ -937,10 +940,11 @@ __global__ void __launch_bounds__(64 * MW) ct_fluid_march(const T* __restrict__ 
 // moves them with the whole-wavefront shifts (wave_shl:1 / wave_shr:1), one
 // VALU move per 32 bits; otherwise they go through the LDS crossbar
 // (ds_bpermute), which costs no VALU issue slot but waits on LDS latency.
-// Measured per kernel: DPP is 1.5-3 % faster for the FP64 fluid sweep, the
-// crossbar 20 % faster for the FP32 fluid sweep (closer to its issue limit);
-// the field sweep shows no difference beyond run-to-run noise and keeps the
-// crossbar.
+// Measured per kernel: DPP is 1.5-3 % faster for the FP64 fluid sweep and
+// 10 % for the field part of the FP64 row-form fused sweep (0.538 -> 0.485 ms
+// per launch at 256^3), the crossbar 20 % faster for the FP32 fluid sweep
+// (closer to its issue limit); the FP32 field sweep shows no difference
+// beyond run-to-run noise and keeps the crossbar.
 __device__ __forceinline__ int dpp_next(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xF, 0xF, false); }
 __device__ __forceinline__ int dpp_prev(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false); }
 
@@ -1424,7 +1428,7 @@ __global__ void __launch_bounds__(64 * XRW) ct_fluid_x_row(const T* __restrict__
     u[3] = uin[3 * N + c];
     u[4] = uin[4 * N + c];
     T vhn[4], vhp[4];
-    X.template shift<4, true, true, false>(vh, vhn, vhp);
+    X.template shift<4, true, true, kDpp>(vh, vhn, vhp);
     T vv[4], qb[4];
 #pragma unroll
     for (int e = 0; e < 4; e++) {
@@ -1437,7 +1441,7 @@ __global__ void __launch_bounds__(64 * XRW) ct_fluid_x_row(const T* __restrict__
         t8[e] = vv[e];
         t8[4 + e] = qb[e];
     }
-    X.template shift<8, true, false, false>(t8, t8n, nullptr);
+    X.template shift<8, true, false, kDpp>(t8, t8n, nullptr);
     T ev[4], g1[4];
 #pragma unroll
     for (int e = 0; e < 4; e++) {
@@ -1445,7 +1449,7 @@ __global__ void __launch_bounds__(64 * XRW) ct_fluid_x_row(const T* __restrict__
         g1[e] = ev[e] > T(0) ? qb[e] : t8n[4 + e];
     }
     T g1p[4];
-    X.template shift<4, false, true, false>(g1, nullptr, g1p);
+    X.template shift<4, false, true, kDpp>(g1, nullptr, g1p);
     T qh[4];
 #pragma unroll
     for (int e = 0; e < 4; e++) {
@@ -1453,17 +1457,17 @@ __global__ void __launch_bounds__(64 * XRW) ct_fluid_x_row(const T* __restrict__
         qh[e] = vv[e] * bhalf;
     }
     T qhn[4], qhp[4];
-    X.template shift<4, true, true, false>(qh, qhn, qhp);
+    X.template shift<4, true, true, kDpp>(qh, qhn, qhp);
     T sq[4];
 #pragma unroll
     for (int e = 0; e < 4; e++) sq[e] = vanleer_half(qh[e] - qhp[e], qhn[e] - qh[e]);
     T sqn[4];
-    X.template shift<4, true, false, false>(sq, sqn, nullptr);
+    X.template shift<4, true, false, kDpp>(sq, sqn, nullptr);
     T G[4];
 #pragma unroll
     for (int e = 0; e < 4; e++) G[e] = ev[e] > T(0) ? qh[e] + sq[e] : qhn[e] - sqn[e];
     T gm[4];
-    X.template shift<4, false, true, false>(G, nullptr, gm);
+    X.template shift<4, false, true, kDpp>(G, nullptr, gm);
     T nB[5];   // B_x, B_y, B_y(+y), B_z, B_z(+z)
     if (frozen) {
         nB[0] = bx;
@@ -1543,7 +1547,7 @@ __global__ void __launch_bounds__(64 * XRW) ct_fluid_x_row(const T* __restrict__
 // The row form applies to periodic rows of 64 k cells, k <= XRW, in FP64,
 // where the wavefront form is bound by instruction issue: 0.607 -> 0.545 ms
 // per launch at 256^3. In FP32 the twelve barriers cost more than the halo
-// lanes save (0.348 -> 0.372 ms), so FP32 keeps the wavefront form.
+// lanes save (0.348 -> 0.372 ms); FP32 runs the lane-row form instead.
 template <typename T>
 static bool ct_fluid_x_row_ok(const Grid& g)
 {
@@ -2068,9 +2072,9 @@ __global__ void __launch_bounds__(256) ct_x_lrow(const T* __restrict__ uf, const
     ct_x_lrow_body<T, K, W>(uf, bin, bout, g, ctl, dt_arg, blockIdx.x);
 }
 
-// fluid_x alone on a lane row (as fluid_x_body); batches use it on rows of 64
-// and 128 cells, where the wavefront form wastes a third to a half of its
-// lanes.
+// fluid_x alone on a lane row (as fluid_x_body), in FP32: plain handles on
+// every row length the form takes, batches on rows of 32 to 128 cells, where
+// the wavefront form wastes a quarter to a half of its lanes.
 // With CFL the rows' largest CFL speed goes to part (all threads take part).
 template <typename T, int K, int W, bool CFL>
 __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* __restrict__ uout,
@@ -2193,10 +2197,10 @@ __global__ void __launch_bounds__(256) fluid_x_lrow(const T* __restrict__ uin, T
 // of 48 four at a time (W = 16, K = 3). Rows of other lengths run the
 // wavefront form. The field update along x takes the form in both precisions
 // (FP64 256^3: 0.303 -> 0.254 ms against the wavefront form); the fluid update
-// and the fused reverse L_x take it in FP32 only: in FP64 the fluid update
-// measured 0.379 ms against 0.357 for the wavefront form, and the fused sweep
-// needs 247-256 VGPRs in this form and runs in the row-per-workgroup form
-// instead.
+// and the fused reverse L_x take it in FP32 only: FP64 periodic rows of 64 k
+// cells run both in the row-per-workgroup form (the FP64 fluid update in the
+// lane-row form measured 0.379 ms, in the row form 0.302; the fused sweep
+// needs 247-256 VGPRs in the lane-row form).
 static int x_lrow_k(const Grid& g, int* W, int kmax = 4)
 {
     if (g.bc != 0) return 0;
