@@ -935,18 +935,21 @@ __global__ void __launch_bounds__(64 * MW) ct_fluid_march(const T* __restrict__ 
 
 
 // Neighbours along a row held in the lanes of one wavefront: lane i receives
-// the value of lane i + 1 (lane_next) or lane i - 1 (lane_prev); the end lane
-// with no source keeps its own value (it is a ghost lane either way). DPP
-// moves them with the whole-wavefront shifts (wave_shl:1 / wave_shr:1), one
-// VALU move per 32 bits; otherwise they go through the LDS crossbar
+// the value of lane i + 1 (lane_next) or lane i - 1 (lane_prev); what the end
+// lane with no source receives is never used (a ghost lane of the wavefront
+// form, or a lane the row form overwrites from LDS): with DPP it is 0 and
+// otherwise its own value. DPP moves them with the whole-wavefront shifts
+// (wave_shl:1 / wave_shr:1), one VALU move per 32 bits (writing 0 into the
+// lane with no source, so the move needs no copy of its operand to keep that
+// lane's old value); otherwise they go through the LDS crossbar
 // (ds_bpermute), which costs no VALU issue slot but waits on LDS latency.
 // Measured per kernel: DPP is 1.5-3 % faster for the FP64 fluid sweep and
 // 10 % for the field part of the FP64 row-form fused sweep (0.538 -> 0.485 ms
 // per launch at 256^3), the crossbar 20 % faster for the FP32 fluid sweep
 // (closer to its issue limit); the FP32 field sweep shows no difference
 // beyond run-to-run noise and keeps the crossbar.
-__device__ __forceinline__ int dpp_next(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xF, 0xF, false); }
-__device__ __forceinline__ int dpp_prev(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_next(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_prev(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true); }
 
 template <bool DPP>
 __device__ __forceinline__ float lane_next(float v)
