@@ -1699,12 +1699,39 @@ __device__ __forceinline__ LRowLanes<W> lrow_lanes()
 template <int W>
 __device__ __forceinline__ int lrow_x(const LRowLanes<W>& L, int q) { return L.xl + W * q; }
 
+// With one row per wavefront (W = 64) the source lanes are a rotation of the
+// wavefront by one lane, which the FP64 sweeps take with the DPP whole-
+// wavefront rotates (wave_rol:1 / wave_ror:1) instead of the LDS crossbar.
+template <typename T>
+constexpr bool kLRowDpp = kExact<T>;
+
+__device__ __forceinline__ int dpp_rol(int v) { return __builtin_amdgcn_mov_dpp(v, 0x134, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_ror(int v) { return __builtin_amdgcn_mov_dpp(v, 0x13C, 0xF, 0xF, false); }
+
+template <bool NEXT>
+__device__ __forceinline__ float lane_rot(float v)
+{
+    return __int_as_float(NEXT ? dpp_rol(__float_as_int(v)) : dpp_ror(__float_as_int(v)));
+}
+
+template <bool NEXT>
+__device__ __forceinline__ double lane_rot(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = NEXT ? dpp_rol((int)b) : dpp_ror((int)b);
+    const int hi = NEXT ? dpp_rol((int)(b >> 32)) : dpp_ror((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 template <typename T, int K, int W>
 __device__ __forceinline__ void lrow_next(const T* v, T* out, const LRowLanes<W>& L)
 {
     T r[K];
 #pragma unroll
-    for (int q = 0; q < K; q++) r[q] = __shfl(v[q], L.src_next, 64);
+    for (int q = 0; q < K; q++) {
+        if constexpr (W == 64 && kLRowDpp<T>) r[q] = lane_rot<true>(v[q]);
+        else r[q] = __shfl(v[q], L.src_next, 64);
+    }
     lrow_seam<T, K, 1>(r, out, L.seam_next, std::make_integer_sequence<int, K>{});
 }
 
@@ -1713,7 +1740,10 @@ __device__ __forceinline__ void lrow_prev(const T* v, T* out, const LRowLanes<W>
 {
     T r[K];
 #pragma unroll
-    for (int q = 0; q < K; q++) r[q] = __shfl(v[q], L.src_prev, 64);
+    for (int q = 0; q < K; q++) {
+        if constexpr (W == 64 && kLRowDpp<T>) r[q] = lane_rot<false>(v[q]);
+        else r[q] = __shfl(v[q], L.src_prev, 64);
+    }
     lrow_seam<T, K, K - 1>(r, out, L.seam_prev, std::make_integer_sequence<int, K>{});
 }
 
