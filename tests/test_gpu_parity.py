@@ -61,9 +61,12 @@ SUBOP_CASES = [
     ((5, 130, 3), 0),
     ((3, 4, 131), 1),
     ((600, 3, 2), 0),
-    # periodic rows of 64 k cells: the x sweeps take their row forms; rows of
-    # 96, 48 and 32 cells share a wavefront in the lane-row field update
+    # periodic rows of 64 k cells: the x sweeps take their row forms (one,
+    # two and three cells per lane in the lane-row field update); rows of 96,
+    # 48 and 32 cells share a wavefront in the lane-row field update
+    ((64, 6, 5), 0),
     ((128, 9, 7), 0),
+    ((192, 5, 3), 0),
     ((96, 7, 5), 0),
     ((48, 9, 4), 0),
     ((32, 5, 6), 0),
@@ -309,8 +312,8 @@ def test_gpu_deterministic(B):
 
 # --------------------------------------------------------------- bitwise FP64
 
-@pytest.mark.parametrize("case", ["random_periodic", "random_outflow", "random_rows", "brio_wu", "orszag_tang",
-                                  "blast"])
+@pytest.mark.parametrize("case", ["random_periodic", "random_outflow", "random_rows", "random_rows_192", "brio_wu",
+                                  "orszag_tang", "blast"])
 def test_fp64_path_reproduces_oracle_bitwise(B, orc, case):
     # the FP64 kernels evaluate the oracle's expressions in the same order
     # without FMA contraction, so the results agree bit for bit; in particular
@@ -319,6 +322,9 @@ def test_fp64_path_reproduces_oracle_bitwise(B, orc, case):
     if case == "random_rows":
         # periodic rows of 128 cells: the row forms of the x sweeps
         s, gamma, shape, bc = P.random_smooth(128, 13, 11, seed=P.MASTER_SEED + 52), H.GAMMA53, (128, 13, 11), 0
+    elif case == "random_rows_192":
+        # rows of 192 cells: three cells per lane in the lane-row field update
+        s, gamma, shape, bc = P.random_smooth(192, 7, 6, seed=P.MASTER_SEED + 53), H.GAMMA53, (192, 7, 6), 0
     elif case.startswith("random"):
         bc = 0 if case == "random_periodic" else 1
         s, gamma, shape = P.random_smooth(29, 23, 19, seed=P.MASTER_SEED + 51), H.GAMMA53, (29, 23, 19)
