@@ -40,6 +40,23 @@ namespace {
 template <typename T>
 constexpr bool kExact = std::is_same<T, double>::value;
 
+// Output stores of the sweeps. A non-temporal store (`nt`) does not keep the
+// written line in the caches. Measured at 256^3 against plain stores: in FP32
+// non-temporal stores in every sweep shorten the step by 2-3 %; in FP64 the
+// step time stays the same, non-temporal stores in some kernels and plain ones
+// in the rest included (kernels that store non-temporally get faster, those
+// that read their output right after get slower by as much), so FP64 keeps
+// plain stores. Results are the same bits either way.
+template <typename T>
+constexpr bool kNtStore = !kExact<T>;
+
+template <typename T>
+__device__ __forceinline__ void put(T* p, T v)
+{
+    if constexpr (kNtStore<T>) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // Division. FP64 quotients must be the correctly rounded ones the oracle
 // gets. The compiler's IEEE division is a Newton-Raphson refinement of the
 // hardware reciprocal followed by a residual correction (Markstein's method),
@@ -569,11 +586,11 @@ __device__ __forceinline__ void fluid_march_body(const T* __restrict__ uin, T* _
                 for (int q = 0; q < 5; q++) un[q] = keep[q];
             }
             const long long co = base + (long long)o * sd;
-            uout[co] = un[0];
-            uout[(1 + D) * N + co] = un[1];
-            uout[(1 + E) * N + co] = un[2];
-            uout[(1 + F) * N + co] = un[3];
-            uout[4 * N + co] = un[4];
+            put(&uout[co], un[0]);
+            put(&uout[(1 + D) * N + co], un[1]);
+            put(&uout[(1 + E) * N + co], un[2]);
+            put(&uout[(1 + F) * N + co], un[3]);
+            put(&uout[4 * N + co], un[4]);
             if constexpr (CFL) {
                 // back to x, y, z order: rotated slot of axis a is (a - D) mod 3
                 const T cc = cfl_speed(un[0], un[1 + (3 - D) % 3], un[1 + (4 - D) % 3], un[1 + (5 - D) % 3],
@@ -699,13 +716,13 @@ __device__ __forceinline__ void ct_march_body(const T* __restrict__ uf, const T*
             const T Gf0 = T_IS_E ? Gx0 : Gt0, Gf0p = T_IS_E ? x0.G5 : t0.G5, Gf1p = T_IS_E ? x1.G5 : t1.G5;
             const T be = T_IS_E ? bto : bxo, bfv = T_IS_E ? bxo : bto;
             if (frozen) {
-                bout[E * N + co] = be;
-                bout[F * N + co] = bfv;
-                bout[D * N + co] = bd;
+                put(&bout[E * N + co], be);
+                put(&bout[F * N + co], bfv);
+                put(&bout[D * N + co], bd);
             } else {
-                bout[E * N + co] = be - dt * (Ge0 - Ge0p);
-                bout[F * N + co] = bfv - dt * (Gf0 - Gf0p);
-                bout[D * N + co] = (bd + dt * (Ge1p - Ge0p)) + dt * (Gf1p - Gf0p);
+                put(&bout[E * N + co], be - dt * (Ge0 - Ge0p));
+                put(&bout[F * N + co], bfv - dt * (Gf0 - Gf0p));
+                put(&bout[D * N + co], (bd + dt * (Ge1p - Ge0p)) + dt * (Gf1p - Gf0p));
             }
         }
         t0.G5 = Gt0;
@@ -866,9 +883,9 @@ __device__ __forceinline__ void ct_fluid_march_body(const T* __restrict__ uin, T
         const int q = h - GB;
         if (active && q >= o0 && q < o1) {
             const long long cq = base + (long long)q * sd;
-            bout[E * N + cq] = T_IS_E ? nT0 : nX0;
-            bout[F * N + cq] = T_IS_E ? nX0 : nT0;
-            bout[D * N + cq] = nD;
+            put(&bout[E * N + cq], T_IS_E ? nT0 : nX0);
+            put(&bout[F * N + cq], T_IS_E ? nX0 : nT0);
+            put(&bout[D * N + cq], nD);
         }
         t0.G5 = Gt0;
         t1.G5 = Gt1;
@@ -890,11 +907,11 @@ __device__ __forceinline__ void ct_fluid_march_body(const T* __restrict__ uin, T
                     for (int k = 0; k < 5; k++) un[k] = keep[k];
                 }
                 const long long co = base + (long long)o * sd;
-                uout[co] = un[0];
-                uout[(1 + D) * N + co] = un[1];
-                uout[(1 + E) * N + co] = un[2];
-                uout[(1 + F) * N + co] = un[3];
-                uout[4 * N + co] = un[4];
+                put(&uout[co], un[0]);
+                put(&uout[(1 + D) * N + co], un[1]);
+                put(&uout[(1 + E) * N + co], un[2]);
+                put(&uout[(1 + F) * N + co], un[3]);
+                put(&uout[4 * N + co], un[4]);
                 if constexpr (CFL) {
                     const T cc = cfl_speed(un[0], un[1 + (3 - D) % 3], un[1 + (4 - D) % 3], un[1 + (5 - D) % 3],
                                            un[4], bo[(3 - D) % 3], bo[(4 - D) % 3], bo[(5 - D) % 3], gamma);
@@ -1063,7 +1080,7 @@ __device__ __forceinline__ void fluid_x_body(const T* __restrict__ uin, T* __res
     unsigned long long best = 0ull;
     if (live && lane >= GF && lane < GF + XW && xu < nx) {
 #pragma unroll
-        for (int q = 0; q < 5; q++) uout[q * N + c] = un[q];
+        for (int q = 0; q < 5; q++) put(&uout[q * N + c], un[q]);
         if constexpr (CFL) {
             const T cc = cfl_speed(un[0], un[1], un[2], un[3], un[4], b[0], b[1], b[2], gamma);
             best = speed_bits(cc);
@@ -1156,13 +1173,13 @@ __device__ __forceinline__ void ct_x_body(const T* __restrict__ uf, const T* __r
     if (lane >= GB && lane < GB + XWC && xu < nx) {
         const T bx = bin[c];
         if (frozen) {
-            bout[c] = bx;
-            bout[N + c] = Bk[0];
-            bout[2 * N + c] = Bk[2];
+            put(&bout[c], bx);
+            put(&bout[N + c], Bk[0]);
+            put(&bout[2 * N + c], Bk[2]);
         } else {
-            bout[N + c] = Bk[0] - dt * (G[0] - gm[0]);
-            bout[2 * N + c] = Bk[2] - dt * (G[2] - gm[2]);
-            bout[c] = (bx + dt * (gm[1] - gm[0])) + dt * (gm[3] - gm[2]);
+            put(&bout[N + c], Bk[0] - dt * (G[0] - gm[0]));
+            put(&bout[2 * N + c], Bk[2] - dt * (G[2] - gm[2]));
+            put(&bout[c], (bx + dt * (gm[1] - gm[0])) + dt * (gm[3] - gm[2]));
         }
     }
 }
@@ -1272,9 +1289,9 @@ __device__ __forceinline__ void ct_fluid_x_body(const T* __restrict__ uin, T* __
     }
     const bool store = live && lane >= GCF && lane < GCF + XWF && xu < nx;
     if (store) {
-        bout[c] = nB[0];
-        bout[N + c] = nB[1];
-        bout[2 * N + c] = nB[3];
+        put(&bout[c], nB[0]);
+        put(&bout[N + c], nB[1]);
+        put(&bout[2 * N + c], nB[3]);
     }
     // ---- fluid update (as in fluid_x_body) on the new field
     T b[3], rr[5], ll[5];
@@ -1307,7 +1324,7 @@ __device__ __forceinline__ void ct_fluid_x_body(const T* __restrict__ uin, T* __
     unsigned long long best = 0ull;
     if (store) {
 #pragma unroll
-        for (int q = 0; q < 5; q++) uout[q * N + c] = un[q];
+        for (int q = 0; q < 5; q++) put(&uout[q * N + c], un[q]);
         if constexpr (CFL) {
             const T cc = cfl_speed(un[0], un[1], un[2], un[3], un[4], b[0], b[1], b[2], gamma);
             best = speed_bits(cc);
@@ -1485,9 +1502,9 @@ __global__ void __launch_bounds__(64 * XRW) ct_fluid_x_row(const T* __restrict__
         nB[4] = Bk[3] - dt * (G[3] - gm[3]);
         nB[0] = (bx + dt * (gm[1] - gm[0])) + dt * (gm[3] - gm[2]);
     }
-    bout[c] = nB[0];
-    bout[N + c] = nB[1];
-    bout[2 * N + c] = nB[3];
+    put(&bout[c], nB[0]);
+    put(&bout[N + c], nB[1]);
+    put(&bout[2 * N + c], nB[3]);
     // ---- fluid update (as in fluid_x_body) on the new field
     T bxn;
     X.template shift<1, true, false, kDpp>(nB, &bxn, nullptr);
@@ -1533,7 +1550,7 @@ __global__ void __launch_bounds__(64 * XRW) ct_fluid_x_row(const T* __restrict__
 #pragma unroll
     for (int q = 0; q < 5; q++) un[q] = frozen ? u[q] : u[q] - dt * (fp[q] - fm[q]);
 #pragma unroll
-    for (int q = 0; q < 5; q++) uout[q * N + c] = un[q];
+    for (int q = 0; q < 5; q++) put(&uout[q * N + c], un[q]);
     if constexpr (CFL) {
         const T cc = cfl_speed(un[0], un[1], un[2], un[3], un[4], b[0], b[1], b[2], gamma);
         unsigned long long best = wave_max_u64(speed_bits(cc));
@@ -1637,7 +1654,7 @@ __global__ void __launch_bounds__(64 * XRW) fluid_x_row(const T* __restrict__ ui
 #pragma unroll
     for (int q = 0; q < 5; q++) un[q] = frozen ? u[q] : u[q] - dt * (fp[q] - fm[q]);
 #pragma unroll
-    for (int q = 0; q < 5; q++) uout[q * N + c] = un[q];
+    for (int q = 0; q < 5; q++) put(&uout[q * N + c], un[q]);
     if constexpr (CFL) {
         const T cc = cfl_speed(un[0], un[1], un[2], un[3], un[4], b[0], b[1], b[2], gamma);
         unsigned long long best = wave_max_u64(speed_bits(cc));
@@ -1966,9 +1983,9 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
         }
         if (live) {
             const long long c = rb + lrow_x(L, q);
-            bout[c] = nB[0][q];
-            bout[N + c] = nB[1][q];
-            bout[2 * N + c] = nB[3][q];
+            put(&bout[c], nB[0][q]);
+            put(&bout[N + c], nB[1][q]);
+            put(&bout[2 * N + c], nB[3][q]);
         }
     }
     // ---- fluid update (as in fluid_x_body) on the new field, set by set where no neighbour is needed
@@ -2043,7 +2060,7 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
         for (int q = 0; q < K; q++) {
             // the new state overwrites u (its old value is not needed any more)
             u[m][q] = frozen ? u[m][q] : u[m][q] - dt * (fp[q] - fm[q]);
-            if (live) uout[m * N + rb + lrow_x(L, q)] = u[m][q];
+            if (live) put(&uout[m * N + rb + lrow_x(L, q)], u[m][q]);
         }
     }
     if constexpr (CFL) {
@@ -2090,9 +2107,9 @@ __device__ __forceinline__ void ct_x_lrow_body(const T* __restrict__ uf, const T
 #pragma unroll
         for (int q = 0; q < K; q++) {
             const long long c = S.rb + lrow_x(S.L, q);
-            bout[c] = nB[0][q];
-            bout[S.N + c] = nB[1][q];
-            bout[2 * S.N + c] = nB[3][q];
+            put(&bout[c], nB[0][q]);
+            put(&bout[S.N + c], nB[1][q]);
+            put(&bout[2 * S.N + c], nB[3][q]);
         }
     }
 }
@@ -2198,7 +2215,7 @@ __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* 
 #pragma unroll
         for (int q = 0; q < K; q++) {
             u[m][q] = frozen ? u[m][q] : u[m][q] - dt * (fp[q] - fm[q]);
-            if (S.live) uout[m * N + S.rb + lrow_x(L, q)] = u[m][q];
+            if (S.live) put(&uout[m * N + S.rb + lrow_x(L, q)], u[m][q]);
         }
     }
     if constexpr (CFL) {
