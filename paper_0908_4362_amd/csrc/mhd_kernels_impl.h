@@ -51,6 +51,15 @@ __device__ __forceinline__ void put(T* p, T v)
     __builtin_nontemporal_store(v, p);
 }
 
+// Loads of values that no other thread of the sweep reads (the conserved
+// fields of a fluid update's own cell) are non-temporal as well: 256^3 step
+// FP64 3.353 -> 3.307 ms, FP32 1.677 -> 1.646 ms.
+template <typename T>
+__device__ __forceinline__ T ldnt(const T* p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
 // Division. FP64 quotients must be the correctly rounded ones the oracle
 // gets. The compiler's IEEE division is a Newton-Raphson refinement of the
 // hardware reciprocal followed by a residual correction (Markstein's method),
@@ -546,11 +555,11 @@ __device__ __forceinline__ void fluid_march_body(const T* __restrict__ uin, T* _
 
     auto load = [&](int h, FluidLoad<T>& L) {
         const long long c = base + (long long)wrap_idx(h, nd, g.bc) * sd;
-        L.u[0] = rho[c];
-        L.u[1] = mD[c];
-        L.u[2] = mE[c];
-        L.u[3] = mF[c];
-        L.u[4] = en[c];
+        L.u[0] = ldnt(&rho[c]);
+        L.u[1] = ldnt(&mD[c]);
+        L.u[2] = ldnt(&mE[c]);
+        L.u[3] = ldnt(&mF[c]);
+        L.u[4] = ldnt(&en[c]);
         L.bd1 = BD[base + (long long)wrap_idx(h + 1, nd, g.bc) * sd];
         L.bt0 = BT[c];
         L.bt1 = BT[c + offT];
@@ -819,9 +828,9 @@ __device__ __forceinline__ void ct_fluid_march_body(const T* __restrict__ uin, T
         L.bx1 = BX[c + xp];
         X.bd = BD[base + (long long)wrap_idx(h - GB, nd, g.bc) * sd];
         const long long cp = base + (long long)wrap_idx(h - GB - 1, nd, g.bc) * sd;
-        X.me = mE[cp];
-        X.mf = mF[cp];
-        X.en = en[cp];
+        X.me = ldnt(&mE[cp]);
+        X.mf = ldnt(&mF[cp]);
+        X.en = ldnt(&en[cp]);
     };
 
     EmfPipe<T> t0, t1, x0, x1;   // TA-face pencils (own, +TA), x-face pencils (own, +x)
@@ -1434,9 +1443,9 @@ __global__ void __launch_bounds__(64 * XRW) ct_fluid_x_row(const T* __restrict__
     T u[5];
     u[0] = r0;
     u[1] = m0;
-    u[2] = uin[2 * N + c];
-    u[3] = uin[3 * N + c];
-    u[4] = uin[4 * N + c];
+    u[2] = ldnt(&uin[2 * N + c]);
+    u[3] = ldnt(&uin[3 * N + c]);
+    u[4] = ldnt(&uin[4 * N + c]);
     T vhn[4], vhp[4];
     X.template shift<4, true, true, kDpp>(vh, vhn, vhp);
     T vv[4], qb[4];
@@ -1597,7 +1606,7 @@ __global__ void __launch_bounds__(64 * XRW) fluid_x_row(const T* __restrict__ ui
 
     T u[5];
 #pragma unroll
-    for (int q = 0; q < 5; q++) u[q] = uin[q * N + c];
+    for (int q = 0; q < 5; q++) u[q] = ldnt(&uin[q * N + c]);
     const T bx = bf[c];
     T b[3];
     b[1] = T(0.5) * (bf[N + c] + bf[N + cyp]);
@@ -1902,9 +1911,9 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
         const long long c = rb + x;
         u[0][q] = uin[c];
         u[1][q] = uin[N + c];
-        u[2][q] = uin[2 * N + c];
-        u[3][q] = uin[3 * N + c];
-        u[4][q] = uin[4 * N + c];
+        u[2][q] = ldnt(&uin[2 * N + c]);
+        u[3][q] = ldnt(&uin[3 * N + c]);
+        u[4][q] = ldnt(&uin[4 * N + c]);
         bx[q] = bin[c];
         Bk[0][q] = bin[N + c];
         Bk[1][q] = bin[N + ryp + x];
@@ -2133,7 +2142,7 @@ __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* 
         const int x = lrow_x(L, q);
         const long long c = S.rb + x;
 #pragma unroll
-        for (int m = 0; m < 5; m++) u[m][q] = uin[m * N + c];
+        for (int m = 0; m < 5; m++) u[m][q] = ldnt(&uin[m * N + c]);
         bx[q] = bf[c];
         b[1][q] = T(0.5) * (bf[N + c] + bf[N + S.ryp + x]);
         b[2][q] = T(0.5) * (bf[2 * N + c] + bf[2 * N + S.rzp + x]);
