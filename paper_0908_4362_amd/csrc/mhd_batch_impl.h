@@ -4,7 +4,11 @@
 // problem by binary search over the per-problem workgroup ranges, then runs
 // the same kernel body as the single-problem launch with that problem's grid,
 // buffers, control block and tile parameters, so every problem gets exactly
-// the arithmetic of a plain solve.
+// the arithmetic of a plain solve. A batched launch sweeps the states of all
+// its problems, which together outgrow the last-level cache, so the bodies
+// run with their default cache policy, non-temporal output stores and
+// read-once loads (512 Alfven problems, 309.6 M cells FP32: 8.70 -> 9.02 G
+// cell-updates/s with the stores, 9.33 -> 9.38 G with the loads as well).
 #pragma once
 #include "mhd_kernels_impl.h"
 

@@ -41,24 +41,27 @@ template <typename T>
 constexpr bool kExact = std::is_same<T, double>::value;
 
 // Output stores of the sweeps: non-temporal (`nt`, the written line is not
-// kept in the caches). Measured at 256^3 against plain stores: FP32 step
-// 1.731 -> 1.691 ms, FP64 3.388 -> 3.352 ms (field update along x -6 %, field
-// marches -1 to -2 %, fused sweeps -1 %, the fluid y march +3 %); results are
-// the same bits either way.
-template <typename T>
+// kept in the caches) or plain, as the launch chooses (nt_policy). Measured at
+// 256^3 against plain stores: FP32 step 1.731 -> 1.691 ms, FP64 3.388 ->
+// 3.352 ms (field update along x -6 %, field marches -1 to -2 %, fused sweeps
+// -1 %, the fluid y march +3 %); results are the same bits either way.
+template <bool NT, typename T>
 __device__ __forceinline__ void put(T* p, T v)
 {
-    __builtin_nontemporal_store(v, p);
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
-// Loads of values that no other thread of the sweep reads are non-temporal
-// as well: the conserved fields of a fluid update's own cell (256^3 step FP64
-// 3.353 -> 3.307 ms, FP32 1.677 -> 1.646 ms), the old B_d of a march's own
-// cell and a row's own x face field (a further -0.8 % / -0.5 %).
-template <typename T>
+// Loads of values that no other thread of the sweep reads follow the same
+// policy: the conserved fields of a fluid update's own cell (256^3 step FP64
+// 3.353 -> 3.307 ms, FP32 1.677 -> 1.646 ms with non-temporal loads), the old
+// B_d of a march's own cell and a row's own x face field (a further -0.8 % /
+// -0.5 %).
+template <bool NT, typename T>
 __device__ __forceinline__ T ldnt(const T* p)
 {
-    return __builtin_nontemporal_load(p);
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
 }
 
 // Division. FP64 quotients must be the correctly rounded ones the oracle
@@ -521,7 +524,7 @@ struct FluidLoad {
     T bx0, bx1;   // x face field on the lower / upper face
 };
 
-template <typename T, int D, bool CFL>
+template <typename T, int D, bool CFL, bool NT = true>
 __device__ __forceinline__ void fluid_march_body(const T* __restrict__ uin, T* __restrict__ uout,
                                                  const T* __restrict__ bf, const Grid& g, T gamma,
                                                  const Ctl* __restrict__ ctl, double dt_arg, int chunk, unsigned lb,
@@ -556,12 +559,12 @@ __device__ __forceinline__ void fluid_march_body(const T* __restrict__ uin, T* _
 
     auto load = [&](int h, FluidLoad<T>& L) {
         const long long c = base + (long long)wrap_idx(h, nd, g.bc) * sd;
-        L.u[0] = ldnt(&rho[c]);
-        L.u[1] = ldnt(&mD[c]);
-        L.u[2] = ldnt(&mE[c]);
-        L.u[3] = ldnt(&mF[c]);
-        L.u[4] = ldnt(&en[c]);
-        L.bd1 = ldnt(&BD[base + (long long)wrap_idx(h + 1, nd, g.bc) * sd]);
+        L.u[0] = ldnt<NT>(&rho[c]);
+        L.u[1] = ldnt<NT>(&mD[c]);
+        L.u[2] = ldnt<NT>(&mE[c]);
+        L.u[3] = ldnt<NT>(&mF[c]);
+        L.u[4] = ldnt<NT>(&en[c]);
+        L.bd1 = ldnt<NT>(&BD[base + (long long)wrap_idx(h + 1, nd, g.bc) * sd]);
         L.bt0 = BT[c];
         L.bt1 = BT[c + offT];
         L.bx0 = BX[c];
@@ -590,11 +593,11 @@ __device__ __forceinline__ void fluid_march_body(const T* __restrict__ uin, T* _
                 for (int q = 0; q < 5; q++) un[q] = keep[q];
             }
             const long long co = base + (long long)o * sd;
-            put(&uout[co], un[0]);
-            put(&uout[(1 + D) * N + co], un[1]);
-            put(&uout[(1 + E) * N + co], un[2]);
-            put(&uout[(1 + F) * N + co], un[3]);
-            put(&uout[4 * N + co], un[4]);
+            put<NT>(&uout[co], un[0]);
+            put<NT>(&uout[(1 + D) * N + co], un[1]);
+            put<NT>(&uout[(1 + E) * N + co], un[2]);
+            put<NT>(&uout[(1 + F) * N + co], un[3]);
+            put<NT>(&uout[4 * N + co], un[4]);
             if constexpr (CFL) {
                 // back to x, y, z order: rotated slot of axis a is (a - D) mod 3
                 const T cc = cfl_speed(un[0], un[1 + (3 - D) % 3], un[1 + (4 - D) % 3], un[1 + (5 - D) % 3],
@@ -615,7 +618,7 @@ __device__ __forceinline__ void store_part_count(int* count)
     if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) *count = (int)gridDim.x;
 }
 
-template <typename T, int D, bool CFL>
+template <typename T, int D, bool CFL, bool NT>
 __global__ void __launch_bounds__(64 * MW) fluid_march(const T* __restrict__ uin, T* __restrict__ uout,
                                                        const T* __restrict__ bf, Grid g, T gamma,
                                                        const Ctl* __restrict__ ctl, double dt_arg, int chunk,
@@ -623,7 +626,7 @@ __global__ void __launch_bounds__(64 * MW) fluid_march(const T* __restrict__ uin
 {
     const unsigned lb = blockIdx.x;
     if constexpr (CFL) store_part_count(count);
-    fluid_march_body<T, D, CFL>(uin, uout, bf, g, gamma, ctl, dt_arg, chunk, lb, parts + blockIdx.x);
+    fluid_march_body<T, D, CFL, NT>(uin, uout, bf, g, gamma, ctl, dt_arg, chunk, lb, parts + blockIdx.x);
 }
 
 // B_{e->d}, B_{f->d} for d = y or z: marching kernel, same launch shape as
@@ -637,7 +640,7 @@ struct CtLoad {
     T rXm, mXm, rXp, mXp, bx0, bx1;
 };
 
-template <typename T, int D>
+template <typename T, int D, bool NT = true>
 __device__ __forceinline__ void ct_march_body(const T* __restrict__ uf, const T* __restrict__ bin,
                                               T* __restrict__ bout, const Grid& g, const Ctl* __restrict__ ctl,
                                               double dt_arg, int chunk, unsigned lb)
@@ -713,7 +716,7 @@ __device__ __forceinline__ void ct_march_body(const T* __restrict__ uf, const T*
         if (active && o >= o0) {
             const long long co = base + (long long)o * sd;
             // *.G5 still hold the EMFs at edge o - 1/2 (updated below)
-            const T bd = ldnt(&BD[co]);
+            const T bd = ldnt<NT>(&BD[co]);
             // e is the cyclic successor of d: the constraint adds the e
             // contribution first
             const T Ge0 = T_IS_E ? Gt0 : Gx0, Ge0p = T_IS_E ? t0.G5 : x0.G5, Ge1p = T_IS_E ? t1.G5 : x1.G5;
@@ -723,9 +726,9 @@ __device__ __forceinline__ void ct_march_body(const T* __restrict__ uf, const T*
             const T nE = frozen ? be : be - dt * (Ge0 - Ge0p);
             const T nF = frozen ? bfv : bfv - dt * (Gf0 - Gf0p);
             const T nD = frozen ? bd : (bd + dt * (Ge1p - Ge0p)) + dt * (Gf1p - Gf0p);
-            put(&bout[E * N + co], nE);
-            put(&bout[F * N + co], nF);
-            put(&bout[D * N + co], nD);
+            put<NT>(&bout[E * N + co], nE);
+            put<NT>(&bout[F * N + co], nF);
+            put<NT>(&bout[D * N + co], nD);
         }
         t0.G5 = Gt0;
         t1.G5 = Gt1;
@@ -746,12 +749,12 @@ __device__ __forceinline__ unsigned xcd_order(unsigned b, unsigned n)
     return x * q + (x < r ? x : r) + b / 8u;
 }
 
-template <typename T, int D>
+template <typename T, int D, bool NT>
 __global__ void __launch_bounds__(64 * MW) ct_march(const T* __restrict__ uf, const T* __restrict__ bin,
                                                     T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
                                                     double dt_arg, int chunk)
 {
-    ct_march_body<T, D>(uf, bin, bout, g, ctl, dt_arg, chunk, xcd_order(blockIdx.x, gridDim.x));
+    ct_march_body<T, D, NT>(uf, bin, bout, g, ctl, dt_arg, chunk, xcd_order(blockIdx.x, gridDim.x));
 }
 
 
@@ -777,7 +780,7 @@ struct FusedLoad {
     T me, mf, en;      // m_e, m_f, E of the fluid head cell h - 5
 };
 
-template <typename T, int D, bool CFL>
+template <typename T, int D, bool CFL, bool NT = true>
 __device__ __forceinline__ void ct_fluid_march_body(const T* __restrict__ uin, T* __restrict__ uout,
                                                     const T* __restrict__ bin, T* __restrict__ bout, const Grid& g,
                                                     T gamma, const Ctl* __restrict__ ctl, double dt_arg, int chunk,
@@ -827,11 +830,11 @@ __device__ __forceinline__ void ct_fluid_march_body(const T* __restrict__ uin, T
         L.mXp = md[c + xp];
         L.bx0 = BX[c];
         L.bx1 = BX[c + xp];
-        X.bd = ldnt(&BD[base + (long long)wrap_idx(h - GB, nd, g.bc) * sd]);
+        X.bd = ldnt<NT>(&BD[base + (long long)wrap_idx(h - GB, nd, g.bc) * sd]);
         const long long cp = base + (long long)wrap_idx(h - GB - 1, nd, g.bc) * sd;
-        X.me = ldnt(&mE[cp]);
-        X.mf = ldnt(&mF[cp]);
-        X.en = ldnt(&en[cp]);
+        X.me = ldnt<NT>(&mE[cp]);
+        X.mf = ldnt<NT>(&mF[cp]);
+        X.en = ldnt<NT>(&en[cp]);
     };
 
     EmfPipe<T> t0, t1, x0, x1;   // TA-face pencils (own, +TA), x-face pencils (own, +x)
@@ -885,9 +888,9 @@ __device__ __forceinline__ void ct_fluid_march_body(const T* __restrict__ uin, T
         const int q = h - GB;
         if (active && q >= o0 && q < o1) {
             const long long cq = base + (long long)q * sd;
-            put(&bout[E * N + cq], T_IS_E ? nT0 : nX0);
-            put(&bout[F * N + cq], T_IS_E ? nX0 : nT0);
-            put(&bout[D * N + cq], nD);
+            put<NT>(&bout[E * N + cq], T_IS_E ? nT0 : nX0);
+            put<NT>(&bout[F * N + cq], T_IS_E ? nX0 : nT0);
+            put<NT>(&bout[D * N + cq], nD);
         }
         t0.G5 = Gt0;
         t1.G5 = Gt1;
@@ -909,11 +912,11 @@ __device__ __forceinline__ void ct_fluid_march_body(const T* __restrict__ uin, T
                     for (int k = 0; k < 5; k++) un[k] = keep[k];
                 }
                 const long long co = base + (long long)o * sd;
-                put(&uout[co], un[0]);
-                put(&uout[(1 + D) * N + co], un[1]);
-                put(&uout[(1 + E) * N + co], un[2]);
-                put(&uout[(1 + F) * N + co], un[3]);
-                put(&uout[4 * N + co], un[4]);
+                put<NT>(&uout[co], un[0]);
+                put<NT>(&uout[(1 + D) * N + co], un[1]);
+                put<NT>(&uout[(1 + E) * N + co], un[2]);
+                put<NT>(&uout[(1 + F) * N + co], un[3]);
+                put<NT>(&uout[4 * N + co], un[4]);
                 if constexpr (CFL) {
                     const T cc = cfl_speed(un[0], un[1 + (3 - D) % 3], un[1 + (4 - D) % 3], un[1 + (5 - D) % 3],
                                            un[4], bo[(3 - D) % 3], bo[(4 - D) % 3], bo[(5 - D) % 3], gamma);
@@ -940,7 +943,7 @@ __device__ __forceinline__ void ct_fluid_march_body(const T* __restrict__ uin, T
     if constexpr (CFL) block_max_to_part<64 * MW>(best, threadIdx.x + 64 * threadIdx.y, part);
 }
 
-template <typename T, int D, bool CFL>
+template <typename T, int D, bool CFL, bool NT>
 __global__ void __launch_bounds__(64 * MW) ct_fluid_march(const T* __restrict__ uin, T* __restrict__ uout,
                                                           const T* __restrict__ bin, T* __restrict__ bout, Grid g,
                                                           T gamma, const Ctl* __restrict__ ctl, double dt_arg,
@@ -948,7 +951,7 @@ __global__ void __launch_bounds__(64 * MW) ct_fluid_march(const T* __restrict__ 
                                                           int* count)
 {
     if constexpr (CFL) store_part_count(count);
-    ct_fluid_march_body<T, D, CFL>(uin, uout, bin, bout, g, gamma, ctl, dt_arg, chunk, blockIdx.x,
+    ct_fluid_march_body<T, D, CFL, NT>(uin, uout, bin, bout, g, gamma, ctl, dt_arg, chunk, blockIdx.x,
                                    parts + blockIdx.x);
 }
 
@@ -1018,7 +1021,7 @@ __device__ __forceinline__ double lane_prev(double v)
 // rows in LDS with a barrier per stage measured 24 % slower.)
 constexpr int XW = 64 - 2 * GF;
 
-template <typename T, bool CFL>
+template <typename T, bool CFL, bool NT = true>
 __device__ __forceinline__ void fluid_x_body(const T* __restrict__ uin, T* __restrict__ uout,
                                              const T* __restrict__ bf, const Grid& g, T gamma,
                                              const Ctl* __restrict__ ctl, double dt_arg, unsigned lb,
@@ -1082,7 +1085,7 @@ __device__ __forceinline__ void fluid_x_body(const T* __restrict__ uin, T* __res
     unsigned long long best = 0ull;
     if (live && lane >= GF && lane < GF + XW && xu < nx) {
 #pragma unroll
-        for (int q = 0; q < 5; q++) put(&uout[q * N + c], un[q]);
+        for (int q = 0; q < 5; q++) put<NT>(&uout[q * N + c], un[q]);
         if constexpr (CFL) {
             const T cc = cfl_speed(un[0], un[1], un[2], un[3], un[4], b[0], b[1], b[2], gamma);
             best = speed_bits(cc);
@@ -1091,14 +1094,14 @@ __device__ __forceinline__ void fluid_x_body(const T* __restrict__ uin, T* __res
     if constexpr (CFL) block_max_to_part<256>(best, threadIdx.x, part);
 }
 
-template <typename T, bool CFL>
+template <typename T, bool CFL, bool NT>
 __global__ void __launch_bounds__(256) fluid_x_wave(const T* __restrict__ uin, T* __restrict__ uout,
                                                     const T* __restrict__ bf, Grid g, T gamma,
                                                     const Ctl* __restrict__ ctl, double dt_arg,
                                                     unsigned long long* __restrict__ parts, int* count)
 {
     if constexpr (CFL) store_part_count(count);
-    fluid_x_body<T, CFL>(uin, uout, bf, g, gamma, ctl, dt_arg, blockIdx.x, parts + blockIdx.x);
+    fluid_x_body<T, CFL, NT>(uin, uout, bf, g, gamma, ctl, dt_arg, blockIdx.x, parts + blockIdx.x);
 }
 
 static unsigned x_wave_blocks(const Grid& g)
@@ -1113,7 +1116,7 @@ static unsigned x_wave_blocks(const Grid& g)
 // by stage, with cross-lane shuffles for the neighbours along x.
 constexpr int XWC = 64 - 2 * GB;
 
-template <typename T>
+template <typename T, bool NT = true>
 __device__ __forceinline__ void ct_x_body(const T* __restrict__ uf, const T* __restrict__ bin,
                                           T* __restrict__ bout, const Grid& g, const Ctl* __restrict__ ctl,
                                           double dt_arg, unsigned lb)
@@ -1178,18 +1181,18 @@ __device__ __forceinline__ void ct_x_body(const T* __restrict__ uf, const T* __r
         const T ny0 = frozen ? Bk[0] : Bk[0] - dt * (G[0] - gm[0]);
         const T nz0 = frozen ? Bk[2] : Bk[2] - dt * (G[2] - gm[2]);
         const T nx0 = frozen ? bx : (bx + dt * (gm[1] - gm[0])) + dt * (gm[3] - gm[2]);
-        put(&bout[N + c], ny0);
-        put(&bout[2 * N + c], nz0);
-        put(&bout[c], nx0);
+        put<NT>(&bout[N + c], ny0);
+        put<NT>(&bout[2 * N + c], nz0);
+        put<NT>(&bout[c], nx0);
     }
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ void __launch_bounds__(256) ct_x_wave(const T* __restrict__ uf, const T* __restrict__ bin,
                                                  T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
                                                  double dt_arg)
 {
-    ct_x_body<T>(uf, bin, bout, g, ctl, dt_arg, blockIdx.x);
+    ct_x_body<T, NT>(uf, bin, bout, g, ctl, dt_arg, blockIdx.x);
 }
 
 static unsigned ct_x_wave_blocks(const Grid& g)
@@ -1208,7 +1211,7 @@ static unsigned ct_x_wave_blocks(const Grid& g)
 // field of a ghost lane that of the cell it maps to.
 constexpr int XWF = 64 - 2 * GCF - 1;
 
-template <typename T, bool CFL>
+template <typename T, bool CFL, bool NT = true>
 __device__ __forceinline__ void ct_fluid_x_body(const T* __restrict__ uin, T* __restrict__ uout,
                                                 const T* __restrict__ bin, T* __restrict__ bout, const Grid& g,
                                                 T gamma, const Ctl* __restrict__ ctl, double dt_arg, unsigned lb,
@@ -1289,9 +1292,9 @@ __device__ __forceinline__ void ct_fluid_x_body(const T* __restrict__ uin, T* __
     }
     const bool store = live && lane >= GCF && lane < GCF + XWF && xu < nx;
     if (store) {
-        put(&bout[c], nB[0]);
-        put(&bout[N + c], nB[1]);
-        put(&bout[2 * N + c], nB[3]);
+        put<NT>(&bout[c], nB[0]);
+        put<NT>(&bout[N + c], nB[1]);
+        put<NT>(&bout[2 * N + c], nB[3]);
     }
     // ---- fluid update (as in fluid_x_body) on the new field
     T b[3], rr[5], ll[5];
@@ -1324,7 +1327,7 @@ __device__ __forceinline__ void ct_fluid_x_body(const T* __restrict__ uin, T* __
     unsigned long long best = 0ull;
     if (store) {
 #pragma unroll
-        for (int q = 0; q < 5; q++) put(&uout[q * N + c], un[q]);
+        for (int q = 0; q < 5; q++) put<NT>(&uout[q * N + c], un[q]);
         if constexpr (CFL) {
             const T cc = cfl_speed(un[0], un[1], un[2], un[3], un[4], b[0], b[1], b[2], gamma);
             best = speed_bits(cc);
@@ -1333,14 +1336,14 @@ __device__ __forceinline__ void ct_fluid_x_body(const T* __restrict__ uin, T* __
     if constexpr (CFL) block_max_to_part<256>(best, threadIdx.x, part);
 }
 
-template <typename T, bool CFL>
+template <typename T, bool CFL, bool NT>
 __global__ void __launch_bounds__(256) ct_fluid_x_wave(const T* __restrict__ uin, T* __restrict__ uout,
                                                        const T* __restrict__ bin, T* __restrict__ bout, Grid g,
                                                        T gamma, const Ctl* __restrict__ ctl, double dt_arg,
                                                        unsigned long long* __restrict__ parts, int* count)
 {
     if constexpr (CFL) store_part_count(count);
-    ct_fluid_x_body<T, CFL>(uin, uout, bin, bout, g, gamma, ctl, dt_arg, blockIdx.x, parts + blockIdx.x);
+    ct_fluid_x_body<T, CFL, NT>(uin, uout, bin, bout, g, gamma, ctl, dt_arg, blockIdx.x, parts + blockIdx.x);
 }
 
 static unsigned ct_fluid_x_blocks(const Grid& g)
@@ -1400,7 +1403,7 @@ struct RowX {
     }
 };
 
-template <typename T, bool CFL>
+template <typename T, bool CFL, bool NT>
 __global__ void __launch_bounds__(64 * XRW) ct_fluid_x_row(const T* __restrict__ uin, T* __restrict__ uout,
                                                            const T* __restrict__ bin, T* __restrict__ bout, Grid g,
                                                            T gamma, const Ctl* __restrict__ ctl, double dt_arg,
@@ -1440,13 +1443,13 @@ __global__ void __launch_bounds__(64 * XRW) ct_fluid_x_row(const T* __restrict__
     Bk[1] = bin[N + cyp];
     Bk[2] = bin[2 * N + c];
     Bk[3] = bin[2 * N + czp];
-    const T bx = ldnt(&bin[c]);
+    const T bx = ldnt<NT>(&bin[c]);
     T u[5];
     u[0] = r0;
     u[1] = m0;
-    u[2] = ldnt(&uin[2 * N + c]);
-    u[3] = ldnt(&uin[3 * N + c]);
-    u[4] = ldnt(&uin[4 * N + c]);
+    u[2] = ldnt<NT>(&uin[2 * N + c]);
+    u[3] = ldnt<NT>(&uin[3 * N + c]);
+    u[4] = ldnt<NT>(&uin[4 * N + c]);
     T vhn[4], vhp[4];
     X.template shift<4, true, true, kDpp>(vh, vhn, vhp);
     T vv[4], qb[4];
@@ -1502,9 +1505,9 @@ __global__ void __launch_bounds__(64 * XRW) ct_fluid_x_row(const T* __restrict__
         nB[4] = Bk[3] - dt * (G[3] - gm[3]);
         nB[0] = (bx + dt * (gm[1] - gm[0])) + dt * (gm[3] - gm[2]);
     }
-    put(&bout[c], nB[0]);
-    put(&bout[N + c], nB[1]);
-    put(&bout[2 * N + c], nB[3]);
+    put<NT>(&bout[c], nB[0]);
+    put<NT>(&bout[N + c], nB[1]);
+    put<NT>(&bout[2 * N + c], nB[3]);
     // ---- fluid update (as in fluid_x_body) on the new field
     T bxn;
     X.template shift<1, true, false, kDpp>(nB, &bxn, nullptr);
@@ -1550,7 +1553,7 @@ __global__ void __launch_bounds__(64 * XRW) ct_fluid_x_row(const T* __restrict__
 #pragma unroll
     for (int q = 0; q < 5; q++) un[q] = frozen ? u[q] : u[q] - dt * (fp[q] - fm[q]);
 #pragma unroll
-    for (int q = 0; q < 5; q++) put(&uout[q * N + c], un[q]);
+    for (int q = 0; q < 5; q++) put<NT>(&uout[q * N + c], un[q]);
     if constexpr (CFL) {
         const T cc = cfl_speed(un[0], un[1], un[2], un[3], un[4], b[0], b[1], b[2], gamma);
         unsigned long long best = wave_max_u64(speed_bits(cc));
@@ -1579,7 +1582,7 @@ static bool ct_fluid_x_row_ok(const Grid& g)
 // wavefront ends exchanged through LDS (six exchanges); the same expressions
 // as fluid_x_body, so the same bits. The wavefront form spends 320 lanes on
 // a 256-cell row (5 wavefronts of 58 stored cells).
-template <typename T, bool CFL>
+template <typename T, bool CFL, bool NT>
 __global__ void __launch_bounds__(64 * XRW) fluid_x_row(const T* __restrict__ uin, T* __restrict__ uout,
                                                         const T* __restrict__ bf, Grid g, T gamma,
                                                         const Ctl* __restrict__ ctl, double dt_arg,
@@ -1607,8 +1610,8 @@ __global__ void __launch_bounds__(64 * XRW) fluid_x_row(const T* __restrict__ ui
 
     T u[5];
 #pragma unroll
-    for (int q = 0; q < 5; q++) u[q] = ldnt(&uin[q * N + c]);
-    const T bx = ldnt(&bf[c]);
+    for (int q = 0; q < 5; q++) u[q] = ldnt<NT>(&uin[q * N + c]);
+    const T bx = ldnt<NT>(&bf[c]);
     T b[3];
     b[1] = T(0.5) * (bf[N + c] + bf[N + cyp]);
     b[2] = T(0.5) * (bf[2 * N + c] + bf[2 * N + czp]);
@@ -1654,7 +1657,7 @@ __global__ void __launch_bounds__(64 * XRW) fluid_x_row(const T* __restrict__ ui
 #pragma unroll
     for (int q = 0; q < 5; q++) un[q] = frozen ? u[q] : u[q] - dt * (fp[q] - fm[q]);
 #pragma unroll
-    for (int q = 0; q < 5; q++) put(&uout[q * N + c], un[q]);
+    for (int q = 0; q < 5; q++) put<NT>(&uout[q * N + c], un[q]);
     if constexpr (CFL) {
         const T cc = cfl_speed(un[0], un[1], un[2], un[3], un[4], b[0], b[1], b[2], gamma);
         unsigned long long best = wave_max_u64(speed_bits(cc));
@@ -1851,7 +1854,7 @@ __device__ __forceinline__ void lrow_emf(const T* __restrict__ uin, const LRowSi
 
 // Field update of ct_x_body on a lane row: from rho and m_x of the row (r, m)
 // and the old faces, the new faces nB = (B_x, B_y, B_y(+y), B_z, B_z(+z)).
-template <typename T, int K, int W>
+template <typename T, int K, int W, bool NT>
 __device__ __forceinline__ void lrow_field(const T* __restrict__ uin, const T* __restrict__ bin, const LRowSite<W>& S,
                                            T dt, bool frozen, const T (&r)[K], const T (&m)[K], T (&nB)[5][K])
 {
@@ -1861,7 +1864,7 @@ __device__ __forceinline__ void lrow_field(const T* __restrict__ uin, const T* _
 #pragma unroll
     for (int q = 0; q < K; q++) {
         const int x = lrow_x(L, q);
-        bx[q] = ldnt(&bin[S.rb + x]);
+        bx[q] = ldnt<NT>(&bin[S.rb + x]);
         B0[q] = bin[N + S.rb + x];
         B1[q] = bin[N + S.ryp + x];
         B2[q] = bin[2 * N + S.rb + x];
@@ -1890,7 +1893,7 @@ __device__ __forceinline__ void lrow_field(const T* __restrict__ uin, const T* _
 }
 
 // Logical workgroup lb holds rows 4 lb .. 4 lb + 3.
-template <typename T, int K, int W, bool CFL>
+template <typename T, int K, int W, bool CFL, bool NT = true>
 __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, T* __restrict__ uout,
                                                      const T* __restrict__ bin, T* __restrict__ bout,
                                                      const Grid& g, T gamma, const Ctl* __restrict__ ctl,
@@ -1912,10 +1915,10 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
         const long long c = rb + x;
         u[0][q] = uin[c];
         u[1][q] = uin[N + c];
-        u[2][q] = ldnt(&uin[2 * N + c]);
-        u[3][q] = ldnt(&uin[3 * N + c]);
-        u[4][q] = ldnt(&uin[4 * N + c]);
-        bx[q] = ldnt(&bin[c]);
+        u[2][q] = ldnt<NT>(&uin[2 * N + c]);
+        u[3][q] = ldnt<NT>(&uin[3 * N + c]);
+        u[4][q] = ldnt<NT>(&uin[4 * N + c]);
+        bx[q] = ldnt<NT>(&bin[c]);
         Bk[0][q] = bin[N + c];
         Bk[1][q] = bin[N + ryp + x];
         Bk[2][q] = bin[2 * N + c];
@@ -1983,9 +1986,9 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
         }
         if (live) {
             const long long c = rb + lrow_x(L, q);
-            put(&bout[c], nB[0][q]);
-            put(&bout[N + c], nB[1][q]);
-            put(&bout[2 * N + c], nB[3][q]);
+            put<NT>(&bout[c], nB[0][q]);
+            put<NT>(&bout[N + c], nB[1][q]);
+            put<NT>(&bout[2 * N + c], nB[3][q]);
         }
     }
     // ---- fluid update (as in fluid_x_body) on the new field, set by set where no neighbour is needed
@@ -2060,7 +2063,7 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
         for (int q = 0; q < K; q++) {
             // the new state overwrites u (its old value is not needed any more)
             u[m][q] = frozen ? u[m][q] : u[m][q] - dt * (fp[q] - fm[q]);
-            if (live) put(&uout[m * N + rb + lrow_x(L, q)], u[m][q]);
+            if (live) put<NT>(&uout[m * N + rb + lrow_x(L, q)], u[m][q]);
         }
     }
     if constexpr (CFL) {
@@ -2074,20 +2077,20 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
     }
 }
 
-template <typename T, int K, int W, bool CFL>
+template <typename T, int K, int W, bool CFL, bool NT>
 __global__ void __launch_bounds__(256) ct_fluid_x_lrow(const T* __restrict__ uin, T* __restrict__ uout,
                                                        const T* __restrict__ bin, T* __restrict__ bout, Grid g,
                                                        T gamma, const Ctl* __restrict__ ctl, double dt_arg,
                                                        unsigned long long* __restrict__ parts, int* count)
 {
     if constexpr (CFL) store_part_count(count);
-    ct_fluid_x_lrow_body<T, K, W, CFL>(uin, uout, bin, bout, g, gamma, ctl, dt_arg, blockIdx.x,
+    ct_fluid_x_lrow_body<T, K, W, CFL, NT>(uin, uout, bin, bout, g, gamma, ctl, dt_arg, blockIdx.x,
                                        parts + blockIdx.x);
 }
 
 // B_{y->x}, B_{z->x} alone on a lane row (as ct_x_body); logical workgroup
 // lb holds rows 4 lb .. 4 lb + 3.
-template <typename T, int K, int W>
+template <typename T, int K, int W, bool NT = true>
 __device__ __forceinline__ void ct_x_lrow_body(const T* __restrict__ uf, const T* __restrict__ bin,
                                                T* __restrict__ bout, const Grid& g, const Ctl* __restrict__ ctl,
                                                double dt_arg, unsigned lb)
@@ -2102,31 +2105,31 @@ __device__ __forceinline__ void ct_x_lrow_body(const T* __restrict__ uf, const T
         r[q] = uf[c];
         m[q] = uf[S.N + c];
     }
-    lrow_field<T, K, W>(uf, bin, S, dt, frozen, r, m, nB);
+    lrow_field<T, K, W, NT>(uf, bin, S, dt, frozen, r, m, nB);
     if (S.live) {
 #pragma unroll
         for (int q = 0; q < K; q++) {
             const long long c = S.rb + lrow_x(S.L, q);
-            put(&bout[c], nB[0][q]);
-            put(&bout[S.N + c], nB[1][q]);
-            put(&bout[2 * S.N + c], nB[3][q]);
+            put<NT>(&bout[c], nB[0][q]);
+            put<NT>(&bout[S.N + c], nB[1][q]);
+            put<NT>(&bout[2 * S.N + c], nB[3][q]);
         }
     }
 }
 
-template <typename T, int K, int W>
+template <typename T, int K, int W, bool NT>
 __global__ void __launch_bounds__(256) ct_x_lrow(const T* __restrict__ uf, const T* __restrict__ bin,
                                                  T* __restrict__ bout, Grid g, const Ctl* __restrict__ ctl,
                                                  double dt_arg)
 {
-    ct_x_lrow_body<T, K, W>(uf, bin, bout, g, ctl, dt_arg, blockIdx.x);
+    ct_x_lrow_body<T, K, W, NT>(uf, bin, bout, g, ctl, dt_arg, blockIdx.x);
 }
 
 // fluid_x alone on a lane row (as fluid_x_body), in FP32: plain handles on
 // every row length the form takes, batches on rows of 32 to 128 cells, where
 // the wavefront form wastes a quarter to a half of its lanes.
 // With CFL the rows' largest CFL speed goes to part (all threads take part).
-template <typename T, int K, int W, bool CFL>
+template <typename T, int K, int W, bool CFL, bool NT = true>
 __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* __restrict__ uout,
                                                   const T* __restrict__ bf, const Grid& g, T gamma,
                                                   const Ctl* __restrict__ ctl, double dt_arg, unsigned lb,
@@ -2143,8 +2146,8 @@ __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* 
         const int x = lrow_x(L, q);
         const long long c = S.rb + x;
 #pragma unroll
-        for (int m = 0; m < 5; m++) u[m][q] = ldnt(&uin[m * N + c]);
-        bx[q] = ldnt(&bf[c]);
+        for (int m = 0; m < 5; m++) u[m][q] = ldnt<NT>(&uin[m * N + c]);
+        bx[q] = ldnt<NT>(&bf[c]);
         b[1][q] = T(0.5) * (bf[N + c] + bf[N + S.ryp + x]);
         b[2][q] = T(0.5) * (bf[2 * N + c] + bf[2 * N + S.rzp + x]);
     }
@@ -2215,7 +2218,7 @@ __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* 
 #pragma unroll
         for (int q = 0; q < K; q++) {
             u[m][q] = frozen ? u[m][q] : u[m][q] - dt * (fp[q] - fm[q]);
-            if (S.live) put(&uout[m * N + S.rb + lrow_x(L, q)], u[m][q]);
+            if (S.live) put<NT>(&uout[m * N + S.rb + lrow_x(L, q)], u[m][q]);
         }
     }
     if constexpr (CFL) {
@@ -2230,14 +2233,14 @@ __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* 
     }
 }
 
-template <typename T, int K, int W, bool CFL>
+template <typename T, int K, int W, bool CFL, bool NT>
 __global__ void __launch_bounds__(256) fluid_x_lrow(const T* __restrict__ uin, T* __restrict__ uout,
                                                     const T* __restrict__ bf, Grid g, T gamma,
                                                     const Ctl* __restrict__ ctl, double dt_arg,
                                                     unsigned long long* __restrict__ parts, int* count)
 {
     if constexpr (CFL) store_part_count(count);
-    fluid_x_lrow_body<T, K, W, CFL>(uin, uout, bf, g, gamma, ctl, dt_arg, blockIdx.x, parts + blockIdx.x);
+    fluid_x_lrow_body<T, K, W, CFL, NT>(uin, uout, bf, g, gamma, ctl, dt_arg, blockIdx.x, parts + blockIdx.x);
 }
 
 // Shape of the lane-row form on a periodic grid: W lanes per row and K cells
@@ -2434,7 +2437,22 @@ hipError_t launch_divb(const T* b, Grid g, unsigned long long* parts, int* npart
     return hipGetLastError();
 }
 
-template <typename T, bool CFL>
+// Cache policy of a sweep's output stores and read-once loads (see put):
+// non-temporal where the state is larger than about two thirds of the 256 MB
+// memory-side last-level cache, plain where the next sweep still finds much
+// of the state there. Step times of the blast, plain / non-temporal: 128^3
+// (128 MiB FP64) 0.549 / 0.618 ms FP64, 0.303 / 0.325 ms FP32; 192^3 (216 MiB
+// FP32) 1.971 / 1.943 ms FP64, 0.930 / 0.904 ms FP32; 256^3 3.393 / 3.313 ms
+// FP64, 1.718 / 1.635 ms FP32.
+constexpr long long kNtStateBytes = 160ll << 20;
+
+template <typename T>
+bool nt_policy(const Grid& g)
+{
+    return 8 * g.N * (long long)sizeof(T) > kNtStateBytes;
+}
+
+template <typename T, bool CFL, bool NT>
 static void fluid_launch(int axis, const T* u_in, T* u_out, const T* b, Grid g, double gamma, Ctl* ctl,
                          double dt, unsigned long long* parts, hipStream_t s)
 {
@@ -2444,26 +2462,26 @@ static void fluid_launch(int axis, const T* u_in, T* u_out, const T* b, Grid g, 
     if (K) {
         const unsigned nb = x_lrow_blocks(g, W);
 #define MHD_LROW_FLUID(KK, WW)                                                                                \
-    hipLaunchKernelGGL((fluid_x_lrow<T, KK, WW, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl, \
+    hipLaunchKernelGGL((fluid_x_lrow<T, KK, WW, CFL, NT>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl, \
                        dt, parts, count);
         MHD_LROW_DISPATCH(K, W, MHD_LROW_FLUID)
 #undef MHD_LROW_FLUID
     } else if (axis == 0 && ct_fluid_x_row_ok<T>(g)) {
-        hipLaunchKernelGGL((fluid_x_row<T, CFL>), dim3((unsigned)((long long)g.n[1] * g.n[2])),
+        hipLaunchKernelGGL((fluid_x_row<T, CFL, NT>), dim3((unsigned)((long long)g.n[1] * g.n[2])),
                            dim3(64 * (g.n[0] / 64)), 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt, parts, count);
     } else if (axis == 0) {
         const unsigned nb = x_wave_blocks(g);
-        hipLaunchKernelGGL((fluid_x_wave<T, CFL>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
+        hipLaunchKernelGGL((fluid_x_wave<T, CFL, NT>), dim3(nb), dim3(256), 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
                            parts, count);
     } else {
         const int chunk = march_chunk(g, axis, GF, kFluidMarchWaves, true);
         const unsigned nb = march_blocks(g, axis, chunk, kMarchXWide<T, false>);
         const dim3 block(64, MW);
         if (axis == 1)
-            hipLaunchKernelGGL((fluid_march<T, 1, CFL>), dim3(nb), block, 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
+            hipLaunchKernelGGL((fluid_march<T, 1, CFL, NT>), dim3(nb), block, 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
                                chunk, parts, count);
         else
-            hipLaunchKernelGGL((fluid_march<T, 2, CFL>), dim3(nb), block, 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
+            hipLaunchKernelGGL((fluid_march<T, 2, CFL, NT>), dim3(nb), block, 0, s, u_in, u_out, b, g, (T)gamma, ctl, dt,
                                chunk, parts, count);
     }
 }
@@ -2472,10 +2490,15 @@ template <typename T>
 hipError_t launch_fluid(int axis, const T* u_in, T* u_out, const T* b, Grid g, double gamma, Ctl* ctl,
                         double dt, unsigned long long* parts, hipStream_t s)
 {
-    if (parts)
-        fluid_launch<T, true>(axis, u_in, u_out, b, g, gamma, ctl, dt, parts, s);
+    const bool nt = nt_policy<T>(g);
+    if (parts && nt)
+        fluid_launch<T, true, true>(axis, u_in, u_out, b, g, gamma, ctl, dt, parts, s);
+    else if (parts)
+        fluid_launch<T, true, false>(axis, u_in, u_out, b, g, gamma, ctl, dt, parts, s);
+    else if (nt)
+        fluid_launch<T, false, true>(axis, u_in, u_out, b, g, gamma, ctl, dt, nullptr, s);
     else
-        fluid_launch<T, false>(axis, u_in, u_out, b, g, gamma, ctl, dt, nullptr, s);
+        fluid_launch<T, false, false>(axis, u_in, u_out, b, g, gamma, ctl, dt, nullptr, s);
     return hipGetLastError();
 }
 
@@ -2504,8 +2527,8 @@ bool fused_reverse_pays(const Grid& g, int axis)
     return axis == 0 || fused_chunk<T>(g, axis) >= 64;
 }
 
-template <typename T>
-hipError_t launch_ct_fluid(int axis, const T* u_in, T* u_out, const T* b_in, T* b_out, Grid g, double gamma,
+template <typename T, bool NT>
+static hipError_t ct_fluid_launch(int axis, const T* u_in, T* u_out, const T* b_in, T* b_out, Grid g, double gamma,
                            Ctl* ctl, double dt, unsigned long long* parts, hipStream_t s)
 {
     if (axis < 0 || axis > 2 || g.bc != 0) return hipErrorInvalidValue;
@@ -2515,10 +2538,10 @@ hipError_t launch_ct_fluid(int axis, const T* u_in, T* u_out, const T* b_in, T* 
         const unsigned nb = x_lrow_blocks(g, W);
 #define MHD_LROW_FUSED(KK, WW)                                                                                \
     if (parts)                                                                                                \
-        hipLaunchKernelGGL((ct_fluid_x_lrow<T, KK, WW, true>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in, b_out, \
+        hipLaunchKernelGGL((ct_fluid_x_lrow<T, KK, WW, true, NT>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in, b_out, \
                            g, (T)gamma, ctl, dt, parts, &ctl->nparts);                                        \
     else                                                                                                      \
-        hipLaunchKernelGGL((ct_fluid_x_lrow<T, KK, WW, false>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in,      \
+        hipLaunchKernelGGL((ct_fluid_x_lrow<T, KK, WW, false, NT>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in,      \
                            b_out, g, (T)gamma, ctl, dt, nullptr, nullptr);
         MHD_LROW_DISPATCH(K, W, MHD_LROW_FUSED)
 #undef MHD_LROW_FUSED
@@ -2528,20 +2551,20 @@ hipError_t launch_ct_fluid(int axis, const T* u_in, T* u_out, const T* b_in, T* 
         const unsigned nb = (unsigned)((long long)g.n[1] * g.n[2]);
         const dim3 block(64 * (g.n[0] / 64));
         if (parts)
-            hipLaunchKernelGGL((ct_fluid_x_row<T, true>), dim3(nb), block, 0, s, u_in, u_out, b_in, b_out, g,
+            hipLaunchKernelGGL((ct_fluid_x_row<T, true, NT>), dim3(nb), block, 0, s, u_in, u_out, b_in, b_out, g,
                                (T)gamma, ctl, dt, parts, &ctl->nparts);
         else
-            hipLaunchKernelGGL((ct_fluid_x_row<T, false>), dim3(nb), block, 0, s, u_in, u_out, b_in, b_out, g,
+            hipLaunchKernelGGL((ct_fluid_x_row<T, false, NT>), dim3(nb), block, 0, s, u_in, u_out, b_in, b_out, g,
                                (T)gamma, ctl, dt, nullptr, nullptr);
         return hipGetLastError();
     }
     if (axis == 0) {
         const unsigned nb = ct_fluid_x_blocks(g);
         if (parts)
-            hipLaunchKernelGGL((ct_fluid_x_wave<T, true>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in, b_out, g,
+            hipLaunchKernelGGL((ct_fluid_x_wave<T, true, NT>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in, b_out, g,
                                (T)gamma, ctl, dt, parts, &ctl->nparts);
         else
-            hipLaunchKernelGGL((ct_fluid_x_wave<T, false>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in, b_out, g,
+            hipLaunchKernelGGL((ct_fluid_x_wave<T, false, NT>), dim3(nb), dim3(256), 0, s, u_in, u_out, b_in, b_out, g,
                                (T)gamma, ctl, dt, nullptr, nullptr);
         return hipGetLastError();
     }
@@ -2549,18 +2572,51 @@ hipError_t launch_ct_fluid(int axis, const T* u_in, T* u_out, const T* b_in, T* 
     const dim3 grid(march_blocks(g, axis, chunk, kMarchXWide<T, true>)), block(64, MW);
     if (parts) {
         if (axis == 1)
-            hipLaunchKernelGGL((ct_fluid_march<T, 1, true>), grid, block, 0, s, u_in, u_out, b_in, b_out, g, (T)gamma,
+            hipLaunchKernelGGL((ct_fluid_march<T, 1, true, NT>), grid, block, 0, s, u_in, u_out, b_in, b_out, g, (T)gamma,
                                ctl, dt, chunk, parts, &ctl->nparts);
         else
-            hipLaunchKernelGGL((ct_fluid_march<T, 2, true>), grid, block, 0, s, u_in, u_out, b_in, b_out, g, (T)gamma,
+            hipLaunchKernelGGL((ct_fluid_march<T, 2, true, NT>), grid, block, 0, s, u_in, u_out, b_in, b_out, g, (T)gamma,
                                ctl, dt, chunk, parts, &ctl->nparts);
     } else {
         if (axis == 1)
-            hipLaunchKernelGGL((ct_fluid_march<T, 1, false>), grid, block, 0, s, u_in, u_out, b_in, b_out, g,
+            hipLaunchKernelGGL((ct_fluid_march<T, 1, false, NT>), grid, block, 0, s, u_in, u_out, b_in, b_out, g,
                                (T)gamma, ctl, dt, chunk, nullptr, nullptr);
         else
-            hipLaunchKernelGGL((ct_fluid_march<T, 2, false>), grid, block, 0, s, u_in, u_out, b_in, b_out, g,
+            hipLaunchKernelGGL((ct_fluid_march<T, 2, false, NT>), grid, block, 0, s, u_in, u_out, b_in, b_out, g,
                                (T)gamma, ctl, dt, chunk, nullptr, nullptr);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ct_fluid(int axis, const T* u_in, T* u_out, const T* b_in, T* b_out, Grid g, double gamma,
+                           Ctl* ctl, double dt, unsigned long long* parts, hipStream_t s)
+{
+    if (nt_policy<T>(g)) return ct_fluid_launch<T, true>(axis, u_in, u_out, b_in, b_out, g, gamma, ctl, dt, parts, s);
+    return ct_fluid_launch<T, false>(axis, u_in, u_out, b_in, b_out, g, gamma, ctl, dt, parts, s);
+}
+
+template <typename T, bool NT>
+static hipError_t ct_launch(int axis, const T* u, const T* b_in, T* b_out, Grid g, const Ctl* ctl, double dt,
+                     hipStream_t s)
+{
+    int W = 64;
+    const int K = axis == 0 ? x_lrow_k(g, &W) : 0;
+    if (K) {
+        const unsigned nb = x_lrow_blocks(g, W);
+#define MHD_LROW_CT(KK, WW) \
+    hipLaunchKernelGGL((ct_x_lrow<T, KK, WW, NT>), dim3(nb), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt);
+        MHD_LROW_DISPATCH(K, W, MHD_LROW_CT)
+#undef MHD_LROW_CT
+    } else if (axis == 0) {
+        hipLaunchKernelGGL((ct_x_wave<T, NT>), dim3(ct_x_wave_blocks(g)), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt);
+    } else {
+        const int chunk = march_chunk(g, axis, GB, kCtMarchWaves<T>, true);
+        const dim3 grid(march_blocks(g, axis, chunk, kMarchXWide<T, true>)), block(64, MW);
+        if (axis == 1)
+            hipLaunchKernelGGL((ct_march<T, 1, NT>), grid, block, 0, s, u, b_in, b_out, g, ctl, dt, chunk);
+        else
+            hipLaunchKernelGGL((ct_march<T, 2, NT>), grid, block, 0, s, u, b_in, b_out, g, ctl, dt, chunk);
     }
     return hipGetLastError();
 }
@@ -2569,25 +2625,8 @@ template <typename T>
 hipError_t launch_ct(int axis, const T* u, const T* b_in, T* b_out, Grid g, const Ctl* ctl, double dt,
                      hipStream_t s)
 {
-    int W = 64;
-    const int K = axis == 0 ? x_lrow_k(g, &W) : 0;
-    if (K) {
-        const unsigned nb = x_lrow_blocks(g, W);
-#define MHD_LROW_CT(KK, WW) \
-    hipLaunchKernelGGL((ct_x_lrow<T, KK, WW>), dim3(nb), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt);
-        MHD_LROW_DISPATCH(K, W, MHD_LROW_CT)
-#undef MHD_LROW_CT
-    } else if (axis == 0) {
-        hipLaunchKernelGGL((ct_x_wave<T>), dim3(ct_x_wave_blocks(g)), dim3(256), 0, s, u, b_in, b_out, g, ctl, dt);
-    } else {
-        const int chunk = march_chunk(g, axis, GB, kCtMarchWaves<T>, true);
-        const dim3 grid(march_blocks(g, axis, chunk, kMarchXWide<T, true>)), block(64, MW);
-        if (axis == 1)
-            hipLaunchKernelGGL((ct_march<T, 1>), grid, block, 0, s, u, b_in, b_out, g, ctl, dt, chunk);
-        else
-            hipLaunchKernelGGL((ct_march<T, 2>), grid, block, 0, s, u, b_in, b_out, g, ctl, dt, chunk);
-    }
-    return hipGetLastError();
+    if (nt_policy<T>(g)) return ct_launch<T, true>(axis, u, b_in, b_out, g, ctl, dt, s);
+    return ct_launch<T, false>(axis, u, b_in, b_out, g, ctl, dt, s);
 }
 
 }  // namespace mhd
