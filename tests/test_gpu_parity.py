@@ -343,6 +343,39 @@ def test_fp64_path_reproduces_oracle_bitwise(B, orc, case):
     assert not bad, (bad, field_errors(got, want))
 
 
+# States above 160 MiB take the sweeps' non-temporal stores and read-once
+# loads (the smaller grids above take plain ones); the arithmetic is the same.
+NT_STATE_BYTES = 160 << 20
+
+
+@pytest.mark.parametrize("shape", [(192, 128, 112), (144, 144, 128)])
+def test_fp64_bitwise_with_non_temporal_accesses(B, orc, shape):
+    # rows of 192 cells run the row and lane-row x sweeps, rows of 144 the
+    # wavefront ones; the whole grid equals the oracle bit for bit
+    nx, ny, nz = shape
+    assert 8 * nx * ny * nz * 8 > NT_STATE_BYTES
+    s = P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 54)
+    g = orc.Grid(nx, ny, nz, H.GAMMA53, 0)
+    note("bitwise non-temporal %s" % (shape,))
+    got, t = gpu_run(B, s, H.GAMMA53, 0, B.MHD_F64, 2)
+    want, tw, _ = orc.run(g, s, 2, 0.7)
+    assert t == tw
+    bad = [f for f in range(8) if not np.array_equal(got[f], want[f])]
+    assert not bad, (bad, field_errors(got, want))
+
+
+def test_fp32_gate_with_non_temporal_accesses(B, orc):
+    nx, ny, nz = 192, 176, 160
+    assert 8 * nx * ny * nz * 4 > NT_STATE_BYTES
+    s = P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 55)
+    g = orc.Grid(nx, ny, nz, H.GAMMA53, 0)
+    note("fp32 non-temporal")
+    got, _ = gpu_run(B, s, H.GAMMA53, 0, B.MHD_F32, 2)
+    want, _, _ = orc.run(g, s, 2, 0.7)
+    for f in range(8):
+        assert H.rel_l1(got[f], want[f]) <= F32_SMOOTH_TOL, f
+
+
 @pytest.mark.parametrize("alpha", [1e-90, 1e90])
 def test_fp64_bitwise_on_scaled_states(B, orc, alpha):
     """rho, m, E scaled by alpha and B by sqrt(alpha) (the same flow: velocities
