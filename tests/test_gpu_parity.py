@@ -357,7 +357,7 @@ def test_fp64_bitwise_with_non_temporal_accesses(B, orc, shape):
     s = P.random_smooth(nx, ny, nz, seed=P.MASTER_SEED + 54)
     g = orc.Grid(nx, ny, nz, H.GAMMA53, 0)
     note("bitwise non-temporal %s" % (shape,))
-    got, t = gpu_run(B, s, H.GAMMA53, 0, B.MHD_F64, 2)
+    got, (t, _) = gpu_run(B, s, H.GAMMA53, 0, B.MHD_F64, 2)
     want, tw, _ = orc.run(g, s, 2, 0.7)
     assert t == tw
     bad = [f for f in range(8) if not np.array_equal(got[f], want[f])]
