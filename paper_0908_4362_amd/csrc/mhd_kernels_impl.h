@@ -20,6 +20,10 @@
 // K cells per lane), a whole row per workgroup (row form, one cell per lane,
 // wavefront ends exchanged through LDS), or 64-cell segments with halo lanes
 // (wavefront form).
+//
+// Cache policy: on states larger than the memory-side last-level cache the
+// sweeps write their outputs and read the values no other thread reads with
+// non-temporal accesses (put, ld_own); smaller states keep plain ones.
 #pragma once
 #include <algorithm>
 #include <type_traits>
@@ -58,7 +62,7 @@ __device__ __forceinline__ void put(T* p, T v)
 // B_d of a march's own cell and a row's own x face field (a further -0.8 % /
 // -0.5 %).
 template <bool NT, typename T>
-__device__ __forceinline__ T ldnt(const T* p)
+__device__ __forceinline__ T ld_own(const T* p)
 {
     if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
@@ -559,12 +563,12 @@ __device__ __forceinline__ void fluid_march_body(const T* __restrict__ uin, T* _
 
     auto load = [&](int h, FluidLoad<T>& L) {
         const long long c = base + (long long)wrap_idx(h, nd, g.bc) * sd;
-        L.u[0] = ldnt<NT>(&rho[c]);
-        L.u[1] = ldnt<NT>(&mD[c]);
-        L.u[2] = ldnt<NT>(&mE[c]);
-        L.u[3] = ldnt<NT>(&mF[c]);
-        L.u[4] = ldnt<NT>(&en[c]);
-        L.bd1 = ldnt<NT>(&BD[base + (long long)wrap_idx(h + 1, nd, g.bc) * sd]);
+        L.u[0] = ld_own<NT>(&rho[c]);
+        L.u[1] = ld_own<NT>(&mD[c]);
+        L.u[2] = ld_own<NT>(&mE[c]);
+        L.u[3] = ld_own<NT>(&mF[c]);
+        L.u[4] = ld_own<NT>(&en[c]);
+        L.bd1 = ld_own<NT>(&BD[base + (long long)wrap_idx(h + 1, nd, g.bc) * sd]);
         L.bt0 = BT[c];
         L.bt1 = BT[c + offT];
         L.bx0 = BX[c];
@@ -716,7 +720,7 @@ __device__ __forceinline__ void ct_march_body(const T* __restrict__ uf, const T*
         if (active && o >= o0) {
             const long long co = base + (long long)o * sd;
             // *.G5 still hold the EMFs at edge o - 1/2 (updated below)
-            const T bd = ldnt<NT>(&BD[co]);
+            const T bd = ld_own<NT>(&BD[co]);
             // e is the cyclic successor of d: the constraint adds the e
             // contribution first
             const T Ge0 = T_IS_E ? Gt0 : Gx0, Ge0p = T_IS_E ? t0.G5 : x0.G5, Ge1p = T_IS_E ? t1.G5 : x1.G5;
@@ -830,11 +834,11 @@ __device__ __forceinline__ void ct_fluid_march_body(const T* __restrict__ uin, T
         L.mXp = md[c + xp];
         L.bx0 = BX[c];
         L.bx1 = BX[c + xp];
-        X.bd = ldnt<NT>(&BD[base + (long long)wrap_idx(h - GB, nd, g.bc) * sd]);
+        X.bd = ld_own<NT>(&BD[base + (long long)wrap_idx(h - GB, nd, g.bc) * sd]);
         const long long cp = base + (long long)wrap_idx(h - GB - 1, nd, g.bc) * sd;
-        X.me = ldnt<NT>(&mE[cp]);
-        X.mf = ldnt<NT>(&mF[cp]);
-        X.en = ldnt<NT>(&en[cp]);
+        X.me = ld_own<NT>(&mE[cp]);
+        X.mf = ld_own<NT>(&mF[cp]);
+        X.en = ld_own<NT>(&en[cp]);
     };
 
     EmfPipe<T> t0, t1, x0, x1;   // TA-face pencils (own, +TA), x-face pencils (own, +x)
@@ -1443,13 +1447,13 @@ __global__ void __launch_bounds__(64 * XRW) ct_fluid_x_row(const T* __restrict__
     Bk[1] = bin[N + cyp];
     Bk[2] = bin[2 * N + c];
     Bk[3] = bin[2 * N + czp];
-    const T bx = ldnt<NT>(&bin[c]);
+    const T bx = ld_own<NT>(&bin[c]);
     T u[5];
     u[0] = r0;
     u[1] = m0;
-    u[2] = ldnt<NT>(&uin[2 * N + c]);
-    u[3] = ldnt<NT>(&uin[3 * N + c]);
-    u[4] = ldnt<NT>(&uin[4 * N + c]);
+    u[2] = ld_own<NT>(&uin[2 * N + c]);
+    u[3] = ld_own<NT>(&uin[3 * N + c]);
+    u[4] = ld_own<NT>(&uin[4 * N + c]);
     T vhn[4], vhp[4];
     X.template shift<4, true, true, kDpp>(vh, vhn, vhp);
     T vv[4], qb[4];
@@ -1610,8 +1614,8 @@ __global__ void __launch_bounds__(64 * XRW) fluid_x_row(const T* __restrict__ ui
 
     T u[5];
 #pragma unroll
-    for (int q = 0; q < 5; q++) u[q] = ldnt<NT>(&uin[q * N + c]);
-    const T bx = ldnt<NT>(&bf[c]);
+    for (int q = 0; q < 5; q++) u[q] = ld_own<NT>(&uin[q * N + c]);
+    const T bx = ld_own<NT>(&bf[c]);
     T b[3];
     b[1] = T(0.5) * (bf[N + c] + bf[N + cyp]);
     b[2] = T(0.5) * (bf[2 * N + c] + bf[2 * N + czp]);
@@ -1864,7 +1868,7 @@ __device__ __forceinline__ void lrow_field(const T* __restrict__ uin, const T* _
 #pragma unroll
     for (int q = 0; q < K; q++) {
         const int x = lrow_x(L, q);
-        bx[q] = ldnt<NT>(&bin[S.rb + x]);
+        bx[q] = ld_own<NT>(&bin[S.rb + x]);
         B0[q] = bin[N + S.rb + x];
         B1[q] = bin[N + S.ryp + x];
         B2[q] = bin[2 * N + S.rb + x];
@@ -1915,10 +1919,10 @@ __device__ __forceinline__ void ct_fluid_x_lrow_body(const T* __restrict__ uin, 
         const long long c = rb + x;
         u[0][q] = uin[c];
         u[1][q] = uin[N + c];
-        u[2][q] = ldnt<NT>(&uin[2 * N + c]);
-        u[3][q] = ldnt<NT>(&uin[3 * N + c]);
-        u[4][q] = ldnt<NT>(&uin[4 * N + c]);
-        bx[q] = ldnt<NT>(&bin[c]);
+        u[2][q] = ld_own<NT>(&uin[2 * N + c]);
+        u[3][q] = ld_own<NT>(&uin[3 * N + c]);
+        u[4][q] = ld_own<NT>(&uin[4 * N + c]);
+        bx[q] = ld_own<NT>(&bin[c]);
         Bk[0][q] = bin[N + c];
         Bk[1][q] = bin[N + ryp + x];
         Bk[2][q] = bin[2 * N + c];
@@ -2146,8 +2150,8 @@ __device__ __forceinline__ void fluid_x_lrow_body(const T* __restrict__ uin, T* 
         const int x = lrow_x(L, q);
         const long long c = S.rb + x;
 #pragma unroll
-        for (int m = 0; m < 5; m++) u[m][q] = ldnt<NT>(&uin[m * N + c]);
-        bx[q] = ldnt<NT>(&bf[c]);
+        for (int m = 0; m < 5; m++) u[m][q] = ld_own<NT>(&uin[m * N + c]);
+        bx[q] = ld_own<NT>(&bf[c]);
         b[1][q] = T(0.5) * (bf[N + c] + bf[N + S.ryp + x]);
         b[2][q] = T(0.5) * (bf[2 * N + c] + bf[2 * N + S.rzp + x]);
     }
