@@ -65,6 +65,7 @@ struct Cohort {
     BJob* jobs = nullptr;
     TileDesc* td[mhd::KIND_COUNT] = {};
     unsigned nblocks[mhd::KIND_COUNT] = {};
+    long long cells = 0;         // total cells of the members (picks the launches' cache policy)
     hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
     double exec_cfl[3] = {0.0, 0.0, 0.0};
 };
@@ -281,6 +282,8 @@ int build_tables(mhd_batch* b, Cohort& c)
         J.g = p.g;
         J.gamma = p.gamma;
     }
+    c.cells = 0;
+    for (const BJob& J : jobs) c.cells += J.g.N;
     for (int k = 0; k < mhd::KIND_COUNT; k++) {
         unsigned first = 0;
         for (int j = 0; j < n; j++) {
@@ -336,7 +339,7 @@ int launch_kind(mhd_batch* b, Cohort& c, int kind, bool cfl_parts, int iu, int i
 {
     const int n = (int)c.ids.size();
     HIPCHK(mhd::launch_batch<T>(kind, cfl_parts, c.jobs, c.td[kind], n, c.nblocks[kind], iu, ib,
-                                b->stream),
+                                b->stream, c.cells),
            "batched launch");
     return MHD_OK;
 }

@@ -4,11 +4,11 @@
 // problem by binary search over the per-problem workgroup ranges, then runs
 // the same kernel body as the single-problem launch with that problem's grid,
 // buffers, control block and tile parameters, so every problem gets exactly
-// the arithmetic of a plain solve. A batched launch sweeps the states of all
-// its problems, which together outgrow the last-level cache, so the bodies
-// run with their default cache policy, non-temporal output stores and
-// read-once loads (512 Alfven problems, 309.6 M cells FP32: 8.70 -> 9.02 G
-// cell-updates/s with the stores, 9.33 -> 9.38 G with the loads as well).
+// the arithmetic of a plain solve. The cache policy of a launch's accesses
+// (non-temporal stores and read-once loads, or plain ones) follows the total
+// state of its problems (512 Alfven problems, 309.6 M cells FP32: 8.70 ->
+// 9.02 G cell-updates/s with non-temporal stores, 9.33 -> 9.38 G with the
+// loads as well).
 #pragma once
 #include "mhd_kernels_impl.h"
 
@@ -29,7 +29,7 @@ __device__ __forceinline__ int find_job(const TileDesc* __restrict__ td, int njo
     return lo;
 }
 
-template <typename T, int D, bool CFL>
+template <typename T, int D, bool CFL, bool NT>
 __global__ void __launch_bounds__(64 * MW) fluid_march_batch(const BJob* __restrict__ jobs,
                                                              const TileDesc* __restrict__ td, int njobs, int iu,
                                                              int ib)
@@ -38,12 +38,12 @@ __global__ void __launch_bounds__(64 * MW) fluid_march_batch(const BJob* __restr
     const BJob& J = jobs[j];
     const Grid g = J.g;
     const unsigned lb = blockIdx.x - td[j].first;
-    fluid_march_body<T, D, CFL>(static_cast<const T*>(J.u[iu]), static_cast<T*>(J.u[iu ^ 1]),
+    fluid_march_body<T, D, CFL, NT>(static_cast<const T*>(J.u[iu]), static_cast<T*>(J.u[iu ^ 1]),
                                 static_cast<const T*>(J.b[ib]), g, (T)J.gamma, J.ctl, -1.0, td[j].p0, lb,
                                 J.parts + lb);
 }
 
-template <typename T, int D>
+template <typename T, int D, bool NT>
 __global__ void __launch_bounds__(64 * MW) ct_march_batch(const BJob* __restrict__ jobs,
                                                           const TileDesc* __restrict__ td, int njobs, int iu, int ib)
 {
@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(64 * MW) ct_march_batch(const BJob* __restrict
     const BJob& J = jobs[j];
     const Grid g = J.g;
     const unsigned lb = blockIdx.x - td[j].first;
-    ct_march_body<T, D>(static_cast<const T*>(J.u[iu]), static_cast<const T*>(J.b[ib]), static_cast<T*>(J.b[ib ^ 1]),
+    ct_march_body<T, D, NT>(static_cast<const T*>(J.u[iu]), static_cast<const T*>(J.b[ib]), static_cast<T*>(J.b[ib ^ 1]),
                         g, J.ctl, -1.0, td[j].p0, lb);
 }
 
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(64 * MW) ct_march_batch(const BJob* __restrict
     case 332: X(3, 32) break;            \
     default: X(3, 16) break;             \
     }
-template <typename T, bool CFL>
+template <typename T, bool CFL, bool NT>
 __global__ void __launch_bounds__(256) fluid_x_batch(const BJob* __restrict__ jobs, const TileDesc* __restrict__ td,
                                                      int njobs, int iu, int ib)
 {
@@ -80,16 +80,16 @@ __global__ void __launch_bounds__(256) fluid_x_batch(const BJob* __restrict__ jo
     if constexpr (!kExact<T>) {
         if (td[j].p0) {
 #define MHD_LROW_BFLUID(KK, WW) \
-    fluid_x_lrow_body<T, KK, WW, CFL>(uin, uout, bf, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
+    fluid_x_lrow_body<T, KK, WW, CFL, NT>(uin, uout, bf, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
             MHD_BATCH_LROW_DISPATCH(td[j].p0, td[j].p1, MHD_LROW_BFLUID)
 #undef MHD_LROW_BFLUID
             return;
         }
     }
-    fluid_x_body<T, CFL>(uin, uout, bf, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
+    fluid_x_body<T, CFL, NT>(uin, uout, bf, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ void __launch_bounds__(256) ct_x_batch(const BJob* __restrict__ jobs, const TileDesc* __restrict__ td,
                                                   int njobs, int iu, int ib)
 {
@@ -102,13 +102,13 @@ __global__ void __launch_bounds__(256) ct_x_batch(const BJob* __restrict__ jobs,
     T* bout = static_cast<T*>(J.b[ib ^ 1]);
     if constexpr (!kExact<T>) {
         if (td[j].p0) {
-#define MHD_LROW_BCT(KK, WW) ct_x_lrow_body<T, KK, WW>(uf, bin, bout, g, J.ctl, -1.0, lb);
+#define MHD_LROW_BCT(KK, WW) ct_x_lrow_body<T, KK, WW, NT>(uf, bin, bout, g, J.ctl, -1.0, lb);
             MHD_BATCH_LROW_DISPATCH(td[j].p0, td[j].p1, MHD_LROW_BCT)
 #undef MHD_LROW_BCT
             return;
         }
     }
-    ct_x_body<T>(uf, bin, bout, g, J.ctl, -1.0, lb);
+    ct_x_body<T, NT>(uf, bin, bout, g, J.ctl, -1.0, lb);
 }
 
 // Lane-row cells per lane (and in *W the lanes per row) a batched x sweep may
@@ -124,7 +124,7 @@ int batch_x_lrow_k(const Grid& g, int* W)
 // Fused reverse L_d (periodic problems only; a cohort runs them only when
 // every member is periodic): y/z as ct_fluid_march, x as ct_fluid_x_body or,
 // with p0 = K, the lane-row form.
-template <typename T, int D, bool CFL>
+template <typename T, int D, bool CFL, bool NT>
 __global__ void __launch_bounds__(64 * MW) ct_fluid_march_batch(const BJob* __restrict__ jobs,
                                                                 const TileDesc* __restrict__ td, int njobs, int iu,
                                                                 int ib)
@@ -133,12 +133,12 @@ __global__ void __launch_bounds__(64 * MW) ct_fluid_march_batch(const BJob* __re
     const BJob& J = jobs[j];
     const Grid g = J.g;
     const unsigned lb = blockIdx.x - td[j].first;
-    ct_fluid_march_body<T, D, CFL>(static_cast<const T*>(J.u[iu]), static_cast<T*>(J.u[iu ^ 1]),
+    ct_fluid_march_body<T, D, CFL, NT>(static_cast<const T*>(J.u[iu]), static_cast<T*>(J.u[iu ^ 1]),
                                    static_cast<const T*>(J.b[ib]), static_cast<T*>(J.b[ib ^ 1]), g, (T)J.gamma, J.ctl,
                                    -1.0, td[j].p0, lb, J.parts + lb);
 }
 
-template <typename T, bool CFL>
+template <typename T, bool CFL, bool NT>
 __global__ void __launch_bounds__(256) ct_fluid_x_batch(const BJob* __restrict__ jobs,
                                                         const TileDesc* __restrict__ td, int njobs, int iu, int ib)
 {
@@ -153,13 +153,13 @@ __global__ void __launch_bounds__(256) ct_fluid_x_batch(const BJob* __restrict__
     if constexpr (!kExact<T>) {
         if (td[j].p0) {
 #define MHD_LROW_BFUSED(KK, WW) \
-    ct_fluid_x_lrow_body<T, KK, WW, CFL>(uin, uout, bin, bout, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
+    ct_fluid_x_lrow_body<T, KK, WW, CFL, NT>(uin, uout, bin, bout, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
             MHD_BATCH_LROW_DISPATCH(td[j].p0, td[j].p1, MHD_LROW_BFUSED)
 #undef MHD_LROW_BFUSED
             return;
         }
     }
-    ct_fluid_x_body<T, CFL>(uin, uout, bin, bout, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
+    ct_fluid_x_body<T, CFL, NT>(uin, uout, bin, bout, g, (T)J.gamma, J.ctl, -1.0, lb, J.parts + lb);
 }
 
 template <typename T>
@@ -248,9 +248,9 @@ unsigned tile_blocks(const Grid& g, int kind, int p0, int p1)
     }
 }
 
-template <typename T>
-hipError_t launch_batch(int kind, bool cfl_parts, const BJob* jobs, const TileDesc* td, int njobs, unsigned nb,
-                        int iu, int ib, hipStream_t s)
+template <typename T, bool NT>
+static hipError_t launch_batch_nt(int kind, bool cfl_parts, const BJob* jobs, const TileDesc* td, int njobs,
+                                  unsigned nb, int iu, int ib, hipStream_t s)
 {
     if (nb == 0 || njobs == 0) return hipSuccess;
     const dim3 mblock(64, MW);
@@ -258,48 +258,59 @@ hipError_t launch_batch(int kind, bool cfl_parts, const BJob* jobs, const TileDe
     case KIND_CFL: hipLaunchKernelGGL((cfl_batch<T>), dim3(nb), dim3(RB), 0, s, jobs, td, njobs, iu, ib); break;
     case KIND_FLUID_X:
         if (cfl_parts)
-            hipLaunchKernelGGL((fluid_x_batch<T, true>), dim3(nb), dim3(256), 0, s, jobs, td, njobs, iu, ib);
+            hipLaunchKernelGGL((fluid_x_batch<T, true, NT>), dim3(nb), dim3(256), 0, s, jobs, td, njobs, iu, ib);
         else
-            hipLaunchKernelGGL((fluid_x_batch<T, false>), dim3(nb), dim3(256), 0, s, jobs, td, njobs, iu, ib);
+            hipLaunchKernelGGL((fluid_x_batch<T, false, NT>), dim3(nb), dim3(256), 0, s, jobs, td, njobs, iu, ib);
         break;
     case KIND_FLUID_Y:
         if (cfl_parts)
-            hipLaunchKernelGGL((fluid_march_batch<T, 1, true>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
+            hipLaunchKernelGGL((fluid_march_batch<T, 1, true, NT>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
         else
-            hipLaunchKernelGGL((fluid_march_batch<T, 1, false>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
+            hipLaunchKernelGGL((fluid_march_batch<T, 1, false, NT>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
         break;
     case KIND_FLUID_Z:
         if (cfl_parts)
-            hipLaunchKernelGGL((fluid_march_batch<T, 2, true>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
+            hipLaunchKernelGGL((fluid_march_batch<T, 2, true, NT>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
         else
-            hipLaunchKernelGGL((fluid_march_batch<T, 2, false>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
+            hipLaunchKernelGGL((fluid_march_batch<T, 2, false, NT>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
         break;
     case KIND_CT_X:
-        hipLaunchKernelGGL((ct_x_batch<T>), dim3(nb), dim3(256), 0, s, jobs, td, njobs, iu, ib);
+        hipLaunchKernelGGL((ct_x_batch<T, NT>), dim3(nb), dim3(256), 0, s, jobs, td, njobs, iu, ib);
         break;
-    case KIND_CT_Y: hipLaunchKernelGGL((ct_march_batch<T, 1>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib); break;
-    case KIND_CT_Z: hipLaunchKernelGGL((ct_march_batch<T, 2>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib); break;
+    case KIND_CT_Y: hipLaunchKernelGGL((ct_march_batch<T, 1, NT>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib); break;
+    case KIND_CT_Z: hipLaunchKernelGGL((ct_march_batch<T, 2, NT>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib); break;
     case KIND_CTFLUID_X:
         if (cfl_parts)
-            hipLaunchKernelGGL((ct_fluid_x_batch<T, true>), dim3(nb), dim3(256), 0, s, jobs, td, njobs, iu, ib);
+            hipLaunchKernelGGL((ct_fluid_x_batch<T, true, NT>), dim3(nb), dim3(256), 0, s, jobs, td, njobs, iu, ib);
         else
-            hipLaunchKernelGGL((ct_fluid_x_batch<T, false>), dim3(nb), dim3(256), 0, s, jobs, td, njobs, iu, ib);
+            hipLaunchKernelGGL((ct_fluid_x_batch<T, false, NT>), dim3(nb), dim3(256), 0, s, jobs, td, njobs, iu, ib);
         break;
     case KIND_CTFLUID_Y:
         if (cfl_parts)
-            hipLaunchKernelGGL((ct_fluid_march_batch<T, 1, true>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
+            hipLaunchKernelGGL((ct_fluid_march_batch<T, 1, true, NT>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
         else
-            hipLaunchKernelGGL((ct_fluid_march_batch<T, 1, false>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
+            hipLaunchKernelGGL((ct_fluid_march_batch<T, 1, false, NT>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
         break;
     case KIND_CTFLUID_Z:
         if (cfl_parts)
-            hipLaunchKernelGGL((ct_fluid_march_batch<T, 2, true>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
+            hipLaunchKernelGGL((ct_fluid_march_batch<T, 2, true, NT>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
         else
-            hipLaunchKernelGGL((ct_fluid_march_batch<T, 2, false>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
+            hipLaunchKernelGGL((ct_fluid_march_batch<T, 2, false, NT>), dim3(nb), mblock, 0, s, jobs, td, njobs, iu, ib);
         break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// A batched launch sweeps the states of all its problems: the cache policy of
+// its accesses follows their total size, as for one grid of that size.
+template <typename T>
+hipError_t launch_batch(int kind, bool cfl_parts, const BJob* jobs, const TileDesc* td, int njobs, unsigned nb,
+                        int iu, int ib, hipStream_t s, long long cells)
+{
+    if (8 * cells * (long long)sizeof(T) > kNtStateBytes)
+        return launch_batch_nt<T, true>(kind, cfl_parts, jobs, td, njobs, nb, iu, ib, s);
+    return launch_batch_nt<T, false>(kind, cfl_parts, jobs, td, njobs, nb, iu, ib, s);
 }
 
 }  // namespace mhd

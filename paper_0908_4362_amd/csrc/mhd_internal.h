@@ -133,10 +133,11 @@ unsigned tile_blocks(const Grid& g, int kind, int p0, int p1);
 // One batched sub-operation over njobs problems (tables in device memory,
 // nblocks = last first + last count). iu / ib select the ping-pong copies
 // read (the other copy is written). With cfl_parts a fluid sweep also stores
-// per-workgroup CFL maxima into each problem's parts.
+// per-workgroup CFL maxima into each problem's parts. cells: the problems'
+// total cell count, which picks the cache policy of the launch's accesses.
 template <typename T>
 hipError_t launch_batch(int kind, bool cfl_parts, const BJob* jobs, const TileDesc* td, int njobs, unsigned nblocks,
-                        int iu, int ib, hipStream_t s);
+                        int iu, int ib, hipStream_t s, long long cells);
 // Per-problem second level of the c_max reduction (td: the producing launch's
 // table) and the dt rule of each problem.
 hipError_t launch_finish_batch(const BJob* jobs, const TileDesc* td, int njobs, double cfl, hipStream_t s);

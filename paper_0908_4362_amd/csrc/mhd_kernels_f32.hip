@@ -23,7 +23,7 @@ template void tile_default<float>(const Grid&, int, int*, int*);
 template void tile_candidates<float>(const Grid&, int, std::vector<std::pair<int, int>>&);
 template unsigned tile_blocks<float>(const Grid&, int, int, int);
 template hipError_t launch_batch<float>(int, bool, const BJob*, const TileDesc*, int, unsigned, int, int,
-                                         hipStream_t);
+                                         hipStream_t, long long);
 template hipError_t launch_diag<float>(const float*, const float*, Grid, double, int, int, int, float*, hipStream_t);
 template hipError_t launch_validate<float>(const float*, const float*, long long, Ctl*, hipStream_t);
 }  // namespace mhd

@@ -100,7 +100,7 @@ template void tile_default<double>(const Grid&, int, int*, int*);
 template void tile_candidates<double>(const Grid&, int, std::vector<std::pair<int, int>>&);
 template unsigned tile_blocks<double>(const Grid&, int, int, int);
 template hipError_t launch_batch<double>(int, bool, const BJob*, const TileDesc*, int, unsigned, int, int,
-                                         hipStream_t);
+                                         hipStream_t, long long);
 template hipError_t launch_diag<double>(const double*, const double*, Grid, double, int, int, int, double*, hipStream_t);
 template hipError_t launch_validate<double>(const double*, const double*, long long, Ctl*, hipStream_t);
 }  // namespace mhd
