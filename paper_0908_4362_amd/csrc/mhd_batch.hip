@@ -554,8 +554,11 @@ int autotune(mhd_batch* b, int reps)
     // one timing per grid shape and boundary condition (the lane-row x sweeps
     // and the fused reverse sweeps apply to periodic grids only)
     std::map<std::array<int, 4>, std::vector<int>> shapes;
-    for (auto& kv : b->probs)
+    long long all_cells = 0;
+    for (auto& kv : b->probs) {
         shapes[{kv.second.g.n[0], kv.second.g.n[1], kv.second.g.n[2], kv.second.g.bc}].push_back(kv.first);
+        all_cells += kv.second.g.N;
+    }
     if (shapes.empty()) return MHD_OK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0), "hipEventCreate");
@@ -579,6 +582,8 @@ int autotune(mhd_batch* b, int reps)
             for (auto& cd : cand) {
                 b->tuned[ShapeKey{g.n[0], g.n[1], g.n[2], g.bc, kind}] = cd;
                 if ((rc = build_tables(b, tmp))) break;
+                // timed under the cache policy of the whole batch's launches
+                tmp.cells = all_cells;
                 // copy 0 -> copy 1 (scratch between steps)
                 if ((rc = launch_kind<T>(b, tmp, kind, false, 0, 0))) break;
                 hipError_t e = hipEventRecord(e0, b->stream);
